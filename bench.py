@@ -1,0 +1,171 @@
+"""Benchmark: decays (histories) per second of the full dosimetry path on the
+synthetic 256x256x320 patient phantom (2x2x3 mm, 27 organs), 10^9 decays per
+job.
+
+One step = one pass of the hot path over a batch of decays:
+  nmd_run_histories (alias decay sampling, Woodcock transport, history-by-
+  history FP64 tally and organ scores)  ->  nmd_get_dose (Eq. 1 dose-rate and
+  uncertainty maps)  ->  nmd_get_organ_dose (Eq. 2, Eq. 3, organ sigma).
+The default 10 steps of 10^8 decays make one 10^9-decay job.  Inputs are
+resident on the GPU before the timed region starts.
+
+Prints one JSON line on stdout.  ``roofline`` describes the transport kernel
+(the dominant one); ``cpu_baseline`` times the CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Ideal (non-divergent) VALU instruction counts per unit of work of the
+# transport kernel, counted in its gfx950 code paths; multiplied by the run's
+# own workload counters they give the algorithmic VALU lane-operations.
+VALU_PER_PHILOX_BLOCK = 100   # 10 rounds: 2 mul_lo, 2 mul_hi, 4 xor, 2 mov
+VALU_PER_UNIFORM = 10         # word select, shift, convert, scale
+VALU_PER_STEP = 43            # free flight, inside test, voxel index, event choice
+VALU_PER_COMPTON = 192        # KN attempt 83 + rotation 62 + energy update 47
+VALU_PER_RAYLEIGH = 92        # Thomson inversion 30 + rotation 62
+VALU_PER_HISTORY = 60         # alias sample, voxel coordinates, photon starts
+VALU_PER_MERGED = 20          # tally and organ flush per distinct voxel
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: one lane-operation per lane per cycle
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+
+
+def valu_ops(stats):
+    blocks = stats["rng_blocks"]
+    return (blocks * VALU_PER_PHILOX_BLOCK + 4 * blocks * VALU_PER_UNIFORM
+            + stats["steps"] * VALU_PER_STEP + stats["compton"] * VALU_PER_COMPTON
+            + stats["rayleigh"] * VALU_PER_RAYLEIGH + stats["histories"] * VALU_PER_HISTORY
+            + stats["merged"] * VALU_PER_MERGED)
+
+
+def cpu_baseline(prob, target_s):
+    """The CPU oracle (exact traversal, FP64) on a bounded sample."""
+    import oracle
+    ph = oracle.Phantom(prob.density, prob.material, [m[0] for m in prob.materials],
+                        [m[1] for m in prob.materials], prob.voxel_cm, label=prob.label,
+                        n_organs=prob.n_organs, activity=prob.activity)
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
+    n0 = 20000
+    t0 = time.perf_counter()
+    oracle.run(ph, n0, 7, n_threads=threads)
+    dt0 = time.perf_counter() - t0
+    n = int(max(n0, min(5e7, n0 * target_s / max(dt0, 1e-3))))
+    t0 = time.perf_counter()
+    tal, _ = oracle.run(ph, n, 8, n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": "%d decays of the same phantom, exact-traversal FP64 oracle, %.1f s"
+                      % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--decays-per-step", type=int, default=10 ** 8)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first copy BYTES with a plain device copy, to scale the "
+                         "HBM byte counters of a profile against a known size")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: multi-GPU history sharding is a design, not "
+              "built (see the design notes); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2111_11687_amd import binding as B
+    from paper_2111_11687_amd import phantoms as P
+
+    if args.copy_calibration:
+        a = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    prob = P.patient_phantom()
+    eng = B.Engine(0)
+    eng.set_problem(0, prob)
+    stream = torch.cuda.current_stream()
+    rate = torch.empty(prob.shape, dtype=torch.float64, device="cuda")
+    rel = torch.empty_like(rate)
+    nd = args.decays_per_step
+    seed = 103
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        B.nmd_run_histories(eng.ctx, 0, nd, seed, None)
+        if ev is not None:
+            ev[1].record(stream)
+        B.nmd_get_dose(eng.ctx, 0, rate, rel)
+        return B.nmd_get_organ_dose(eng.ctx, 0, prob.n_organs)
+
+    for _ in range(args.warmup):
+        step()
+    B.nmd_reset_tallies(eng.ctx, 0)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        organs = step(evs[i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    stats = eng.stats(0)
+    led = eng.ledger(0)
+    total = args.steps * nd
+    value = total / dt
+
+    ops_launch = valu_ops(stats) / args.steps
+    achieved = ops_launch / (kern_ms * 1e-3)
+    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"]
+    balance = (dep + led["escaped"] + led["discarded"]) / led["emitted"] - 1.0
+    print(json.dumps({"steps_ms": [round(a.elapsed_time(b), 3) for a, b in evs],
+                      "stats_per_decay": {k: v / total for k, v in stats.items()},
+                      "ledger_balance": balance,
+                      "organ_rate_gy_s": organs[0][:5].tolist(),
+                      "organ_rel_sigma": organs[2][:5].tolist()}), file=sys.stderr)
+    out = {
+        "metric": "histories/s (10^9-decay phantom)",
+        "value": value,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "patient phantom 256x256x320 voxels 2x2x3 mm, 27 organs, "
+                               "lognormal FDG-like activity, 2 photons per decay",
+                   "decays_per_step": nd, "decays_per_job": total,
+                   "tally": "f64", "transport": "f32"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "transport_kernel", "kernel_ms": kern_ms,
+                     "ops_per_decay": ops_launch / nd},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

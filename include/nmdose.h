@@ -1,0 +1,217 @@
+/*
+ * nmdose.h -- C ABI of the MI355X voxel Monte Carlo dosimetry engine.
+ *
+ * The engine computes the internal-dosimetry quantities of ARCHER-NM
+ * (Peng et al., arXiv 2111.11687):
+ *   - decays sampled from a PET activity map through a probability density
+ *     proportional to the activity concentration (Section 2.1);
+ *   - two back-to-back 0.511 MeV annihilation photons per decay with an
+ *     isotropic direction drawn by Marsaglia's method (Section 2.1);
+ *   - photon transport with Compton scattering (free-electron Klein-Nishina),
+ *     the photoelectric effect and a Thomson-shaped Rayleigh term, a 10 keV
+ *     photon cutoff, and local deposit of electron energy (Section 2.1);
+ *   - a voxel dose tally with history-by-history uncertainty (Section 2.1);
+ *   - the dose-rate map of Eq. 1 and the organ mean (Eq. 2) and organ
+ *     uncertainty (Eq. 3) of Section 2.4.
+ *
+ * Conventions
+ *   Arrays are C order [nz][ny][nx] with x fastest.  Voxel sizes are given in
+ *   mm; internally lengths are cm and energies MeV.  Density is g/cm^3,
+ *   activity concentration Bq/mL, dose rate Gy/s.
+ *   Pointers documented as "device" must be device memory of the context's
+ *   device (for example a torch tensor's data_ptr()); "host" pointers are
+ *   ordinary CPU memory.  Input pointers stay owned by the caller and are
+ *   only read during the call.  The library copies what it keeps into its
+ *   own allocations, released by nmd_destroy (or when a phantom is
+ *   re-registered).  Outputs are written into caller buffers.
+ *   All device work is ordered on the context stream.  nmd_run_histories and
+ *   nmd_get_dose are asynchronous with respect to the host; nmd_set_phantom,
+ *   nmd_set_activity, nmd_get_organ_dose and the nmd_get_ledger /
+ *   nmd_get_run_stats readers synchronise the stream.
+ *   Every call returns a status and never aborts; the message of the last
+ *   failure is available from nmd_last_error.  After NMD_E_HIP the context
+ *   must be destroyed.  A context is used by one host thread at a time.
+ */
+#ifndef NMDOSE_H
+#define NMDOSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmd_ctx nmd_ctx;
+typedef int32_t nmd_status;
+
+enum {
+  NMD_OK = 0,
+  NMD_E_INVALID = -1,     /* bad argument value                          */
+  NMD_E_SHAPE = -2,       /* dimensions out of range or inconsistent      */
+  NMD_E_STATE = -3,       /* call out of order (e.g. run before activity) */
+  NMD_E_OOM = -4,         /* device allocation failed                     */
+  NMD_E_HIP = -5,         /* HIP runtime error; the context is unusable   */
+  NMD_E_ABORTED = -6,     /* run stopped by the abort hook                */
+  NMD_E_UNSUPPORTED = -7  /* input outside what this build handles        */
+};
+
+/* One material: effective atomic number and electron fraction Z/A.  The
+ * photoelectric cross section scales as Z^4/E^3 per atom and the Rayleigh
+ * term as Z^2/E^2; Compton is Klein-Nishina per electron. */
+typedef struct {
+  double z_eff;
+  double z_over_a;
+} nmd_material;
+
+/* Run options (nmd_run_opts_default fills the defaults). */
+typedef struct {
+  uint32_t photons_per_decay;  /* 2 (annihilation pair) or 1 (point photon source) */
+  uint32_t process_mask;       /* bit0 Compton, bit1 photoelectric, bit2 Rayleigh; 7 = all */
+  uint32_t max_real_events;    /* per photon; 0 = unlimited; after the limit the photon
+                                  is dropped and its energy booked as "discarded"      */
+  float photon_cutoff_mev;     /* 0.010 (Section 2.1)                                   */
+  uint32_t source_kind;        /* 0 activity map; 1 pencil beam (one photon, fixed
+                                  origin and direction, no source draws)               */
+  float pencil_origin_cm[3];   /* inside the grid                                      */
+  float pencil_dir[3];         /* normalised by the library                            */
+  uint32_t chunk;              /* histories per work-queue claim; 0 = tuned default    */
+  uint32_t grid_blocks;        /* persistent workgroups; 0 = fill the device           */
+  uint32_t abort_after_chunks; /* failure hook: stop after this many claims; 0 = off   */
+  double *history_records;     /* device [n_decays][10] or NULL: per-history debug
+                                  record (edep, escaped, n_compton, n_pe, n_rayleigh,
+                                  n_steps, sum of deposit voxel indices, n distinct
+                                  deposit voxels, uniforms drawn, discarded energy)    */
+} nmd_run_opts;
+
+/* Ledger slots (MeV) and run-stats slots. */
+enum { NMD_LEDGER_EMITTED = 0, NMD_LEDGER_DEP_COMPTON, NMD_LEDGER_DEP_PE, NMD_LEDGER_DEP_CUTOFF,
+       NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_N };
+enum { NMD_STAT_HISTORIES = 0, NMD_STAT_PHOTONS, NMD_STAT_STEPS, NMD_STAT_NULLS,
+       NMD_STAT_COMPTON, NMD_STAT_PE, NMD_STAT_RAYLEIGH, NMD_STAT_DEPOSITS, NMD_STAT_MERGED,
+       NMD_STAT_MAX_MERGED, NMD_STAT_ESCAPES, NMD_STAT_OVERFLOWS, NMD_STAT_CLAIMS,
+       NMD_STAT_RNG_BLOCKS, NMD_STAT_N };
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context. */
+nmd_status nmd_create(nmd_ctx **out, int device, void *hip_stream);
+/* Release every library allocation of the context.  NULL is accepted. */
+void nmd_destroy(nmd_ctx *ctx);
+/* Message of the last failed call on ctx (static text if ctx is NULL). */
+const char *nmd_last_error(const nmd_ctx *ctx);
+/* Change the stream later calls are ordered on. */
+nmd_status nmd_set_stream(nmd_ctx *ctx, void *hip_stream);
+/* Fill *opts with the defaults: 2 photons, all processes, 10 keV cutoff,
+ * activity source, tuned chunk and grid. */
+void nmd_run_opts_default(nmd_run_opts *opts);
+
+/* ---- problem set-up ----------------------------------------------------- */
+
+/* Register (or replace) phantom `phantom_id` (0..63): the CT-derived
+ * density and material grid of Section 2.1 plus an optional organ label map
+ * (Section 2.3).  density: device float[nvox], finite and > 0;
+ * material: device uint8[nvox], < n_materials; organ_label: device
+ * uint8[nvox] or NULL, 0 = no organ, 1..n_organs; materials: host
+ * [n_materials], n_materials <= 8.  nvox = nx*ny*nz must be < 2^31.
+ * Re-registering an id drops its activity and tallies.  Distinct
+ * (material, density) pairs over all phantoms of a context are limited to
+ * 256 (NMD_E_UNSUPPORTED beyond).  Synchronises the stream. */
+nmd_status nmd_set_phantom(nmd_ctx *ctx, int32_t phantom_id, int32_t nx, int32_t ny, int32_t nz,
+                           float dx_mm, float dy_mm, float dz_mm, const float *density,
+                           const uint8_t *material, const uint8_t *organ_label,
+                           int32_t n_organs, const nmd_material *materials, int32_t n_materials);
+
+/* Set the activity map of a phantom: the decay probability of a voxel is
+ * proportional to its activity concentration (the linear conversion of
+ * Section 2.1).  activity_bq_ml: device float[nvox], finite, >= 0, not all
+ * zero.  total_activity_bq is A(t_s) of Eq. 1; <= 0 means sum(A_v * V_v)
+ * with V_v in mL.  Resets the phantom's tallies.  Synchronises the stream. */
+nmd_status nmd_set_activity(nmd_ctx *ctx, int32_t phantom_id, const float *activity_bq_ml,
+                            double total_activity_bq);
+
+/* ---- transport ----------------------------------------------------------- */
+
+/* Simulate n_decays histories of phantom `phantom_id`, or of every phantom
+ * with an activity map when phantom_id is -1 (one persistent launch over a
+ * shared work queue), adding to the phantom's tallies.  Histories are
+ * numbered from the number already run since the last reset, and history h
+ * of phantom p draws its random numbers from Philox4x32-10 with key = seed
+ * and counter = (block, h, p), so repeated calls continue one stream and the
+ * result does not depend on the launch shape.  opts NULL = defaults.
+ * Asynchronous; returns NMD_E_ABORTED (after synchronising) when the abort
+ * hook fired. */
+nmd_status nmd_run_histories(nmd_ctx *ctx, int32_t phantom_id, uint64_t n_decays, uint64_t seed,
+                             const nmd_run_opts *opts);
+
+/* Zero the tallies, ledger, statistics and history counter of a phantom
+ * (-1 = all). */
+nmd_status nmd_reset_tallies(nmd_ctx *ctx, int32_t phantom_id);
+
+/* ---- results ------------------------------------------------------------- */
+
+/* Dose-rate map of Eq. 1: (S_v / N) * c / m_v * A(t_s), with S_v the
+ * deposited energy of voxel v, N the decays run since the last reset,
+ * c = 1.602176634e-13 J/MeV and m_v the voxel mass; and the relative
+ * history-by-history standard error s_v / D_v (0 where nothing was
+ * deposited).  dose_rate_gy_s: device double[nvox]; rel_uncertainty:
+ * device double[nvox] or NULL.  Asynchronous. */
+nmd_status nmd_get_dose(nmd_ctx *ctx, int32_t phantom_id, double *dose_rate_gy_s,
+                        double *rel_uncertainty);
+
+/* Organ statistics for labels 1..n_organs (host arrays of n_organs, any may
+ * be NULL): Eq. 2 mean voxel dose rate, Eq. 3 root-mean-square voxel
+ * relative uncertainty, and the relative standard error of the organ mean
+ * from per-history organ scores.  Synchronises the stream. */
+nmd_status nmd_get_organ_dose(nmd_ctx *ctx, int32_t phantom_id, int32_t n_organs,
+                              double *dose_rate_gy_s, double *eps_eq3, double *rel_sigma_mean);
+
+/* Organ dose rate from the per-history organ scores (A * O_o / N), which
+ * equals Eq. 2 up to rounding; host double[n_organs].  Synchronises. */
+nmd_status nmd_get_organ_score(nmd_ctx *ctx, int32_t phantom_id, int32_t n_organs,
+                               double *dose_rate_gy_s);
+
+/* Energy ledger of a phantom (host double[NMD_LEDGER_N], MeV) and run
+ * counters (host uint64_t[NMD_STAT_N]).  Synchronise the stream. */
+nmd_status nmd_get_ledger(nmd_ctx *ctx, int32_t phantom_id, double *ledger);
+nmd_status nmd_get_run_stats(nmd_ctx *ctx, int32_t phantom_id, uint64_t *stats);
+
+/* Raw accumulated sums: S_v (MeV) and S2_v (MeV^2) into device
+ * double[nvox] buffers (either may be NULL), and the number of decays N.
+ * Asynchronous. */
+nmd_status nmd_get_tallies(nmd_ctx *ctx, int32_t phantom_id, double *sum_dev, double *sum2_dev,
+                           uint64_t *n_decays);
+
+/* Replace the sums S_v, S2_v (device or host double[nvox] each) and the
+ * decay count N of a phantom, e.g. to resume from values read with
+ * nmd_get_tallies.  The per-history organ scores, ledger and counters are
+ * zeroed.  Synchronises the stream. */
+nmd_status nmd_set_tallies(nmd_ctx *ctx, int32_t phantom_id, const double *sum,
+                           const double *sum2, uint64_t n_decays);
+
+/* ---- test hooks ----------------------------------------------------------- */
+
+/* Draw n samples with the device samplers the transport kernel uses; sample
+ * i uses the random stream of history i of phantom 0.  kind: 0 raw Philox
+ * words (4 per sample), 1 uniform, 2 Marsaglia direction (3), 3 Klein-Nishina
+ * (eps = E'/E, cos theta) at e_mev, 5 Thomson cos theta.  out: device
+ * double[n * width].  Asynchronous. */
+nmd_status nmd_debug_sample(nmd_ctx *ctx, int32_t kind, double e_mev, uint64_t n, uint64_t seed,
+                            double *out);
+
+/* Draw n decay voxels of phantom `phantom_id` with its alias table; sample
+ * i uses the stream of history i.  out: device uint32[n].  Asynchronous. */
+nmd_status nmd_debug_sample_source(nmd_ctx *ctx, int32_t phantom_id, uint64_t n, uint64_t seed,
+                                   uint32_t *out);
+
+/* Evaluate, in the transport kernel's FP32 arithmetic, the majorant of
+ * phantom `phantom_id` and the largest attenuation coefficient over its
+ * (material, density) pairs at n energies.  energies: device float[n];
+ * out: device float[2n] (majorant, max mu).  Asynchronous. */
+nmd_status nmd_debug_xs(nmd_ctx *ctx, int32_t phantom_id, uint64_t n, const float *energies,
+                        float *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMDOSE_H */

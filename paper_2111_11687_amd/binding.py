@@ -1,0 +1,313 @@
+"""Thin ctypes binding of ``libnmdose.so`` (the C ABI in include/nmdose.h).
+
+Every ``nmd_*`` function here marshals its arguments and calls the C entry
+point of the same name; all computation runs in the HIP kernels.  PyTorch is
+used only to hold device memory and to supply the stream.  There is no CPU
+fallback: if the library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnmdose.so")
+
+LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded")
+STATS_FIELDS = ("histories", "photons", "steps", "nulls", "compton", "photoelectric",
+                "rayleigh", "deposits", "merged", "max_merged", "escapes", "overflows",
+                "claims", "rng_blocks")
+HREC_FIELDS = ("edep", "escaped", "n_compton", "n_pe", "n_rayleigh", "n_steps",
+               "sum_voxel", "n_merged", "n_uniforms", "discarded")
+STATUS = {0: "NMD_OK", -1: "NMD_E_INVALID", -2: "NMD_E_SHAPE", -3: "NMD_E_STATE",
+          -4: "NMD_E_OOM", -5: "NMD_E_HIP", -6: "NMD_E_ABORTED", -7: "NMD_E_UNSUPPORTED"}
+
+
+class NmdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class nmd_material(ctypes.Structure):
+    _fields_ = [("z_eff", ctypes.c_double), ("z_over_a", ctypes.c_double)]
+
+
+class nmd_run_opts(ctypes.Structure):
+    _fields_ = [("photons_per_decay", ctypes.c_uint32), ("process_mask", ctypes.c_uint32),
+                ("max_real_events", ctypes.c_uint32), ("photon_cutoff_mev", ctypes.c_float),
+                ("source_kind", ctypes.c_uint32), ("pencil_origin_cm", ctypes.c_float * 3),
+                ("pencil_dir", ctypes.c_float * 3), ("chunk", ctypes.c_uint32),
+                ("grid_blocks", ctypes.c_uint32), ("abort_after_chunks", ctypes.c_uint32),
+                ("history_records", ctypes.c_void_p)]
+
+
+EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
+           "nmd_run_opts_default", "nmd_set_phantom", "nmd_set_activity", "nmd_run_histories",
+           "nmd_reset_tallies", "nmd_get_dose", "nmd_get_organ_dose", "nmd_get_organ_score",
+           "nmd_get_ledger", "nmd_get_run_stats", "nmd_get_tallies", "nmd_set_tallies",
+           "nmd_debug_sample",
+           "nmd_debug_sample_source", "nmd_debug_xs")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (torch first, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libnmdose.so is not built (run paper_2111_11687_amd/build.py)")
+    import torch  # noqa: F401  (loads the HIP runtime the library will bind to)
+    L = ctypes.CDLL(path)
+    vp, i32, u64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "nmd_create": [ctypes.POINTER(vp), ctypes.c_int, vp],
+        "nmd_destroy": [vp],
+        "nmd_last_error": [vp],
+        "nmd_set_stream": [vp, vp],
+        "nmd_run_opts_default": [ctypes.POINTER(nmd_run_opts)],
+        "nmd_set_phantom": [vp, i32, i32, i32, i32, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, vp, vp, vp, i32, ctypes.POINTER(nmd_material), i32],
+        "nmd_set_activity": [vp, i32, vp, d],
+        "nmd_run_histories": [vp, i32, u64, u64, ctypes.POINTER(nmd_run_opts)],
+        "nmd_reset_tallies": [vp, i32],
+        "nmd_get_dose": [vp, i32, vp, vp],
+        "nmd_get_organ_dose": [vp, i32, i32, vp, vp, vp],
+        "nmd_get_organ_score": [vp, i32, i32, vp],
+        "nmd_get_ledger": [vp, i32, vp],
+        "nmd_get_run_stats": [vp, i32, vp],
+        "nmd_get_tallies": [vp, i32, vp, vp, ctypes.POINTER(u64)],
+        "nmd_set_tallies": [vp, i32, vp, vp, u64],
+        "nmd_debug_sample": [vp, i32, d, u64, u64, vp],
+        "nmd_debug_sample_source": [vp, i32, u64, u64, vp],
+        "nmd_debug_xs": [vp, i32, u64, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.nmd_destroy.restype = None
+    L.nmd_run_opts_default.restype = None
+    L.nmd_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(ctx, status):
+    if status != 0:
+        msg = load_library().nmd_last_error(ctx)
+        raise NmdError(status, msg.decode() if msg else "")
+
+
+def _dptr(t):
+    """Device address of a torch tensor (or None)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---- one wrapper per C entry point -----------------------------------------
+def nmd_create(device: int = 0, stream=None):
+    L = load_library()
+    h = ctypes.c_void_p()
+    st = L.nmd_create(ctypes.byref(h), int(device), _stream_handle(stream))
+    if st != 0:
+        raise NmdError(st, "nmd_create failed on device %d" % device)
+    return h
+
+
+def nmd_destroy(ctx):
+    load_library().nmd_destroy(ctx)
+
+
+def nmd_last_error(ctx) -> str:
+    m = load_library().nmd_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def nmd_set_stream(ctx, stream=None):
+    _check(ctx, load_library().nmd_set_stream(ctx, _stream_handle(stream)))
+
+
+def nmd_run_opts_default() -> nmd_run_opts:
+    o = nmd_run_opts()
+    load_library().nmd_run_opts_default(ctypes.byref(o))
+    return o
+
+
+def nmd_set_phantom(ctx, phantom_id, density, material, organ_label, n_organs, materials,
+                    voxel_mm):
+    """density float32, material uint8, organ_label uint8 or None: torch
+    device tensors of shape (nz, ny, nx); materials: [(z_eff, z_over_a)]."""
+    nz, ny, nx = density.shape
+    arr = (nmd_material * len(materials))(*[nmd_material(float(z), float(a))
+                                            for z, a in materials])
+    _check(ctx, load_library().nmd_set_phantom(
+        ctx, int(phantom_id), nx, ny, nz, float(voxel_mm[0]), float(voxel_mm[1]),
+        float(voxel_mm[2]), _dptr(density), _dptr(material), _dptr(organ_label), int(n_organs),
+        arr, len(materials)))
+
+
+def nmd_set_activity(ctx, phantom_id, activity, total_activity_bq=0.0):
+    _check(ctx, load_library().nmd_set_activity(ctx, int(phantom_id), _dptr(activity),
+                                                float(total_activity_bq)))
+
+
+def nmd_run_histories(ctx, phantom_id, n_decays, seed, opts: nmd_run_opts | None = None):
+    _check(ctx, load_library().nmd_run_histories(
+        ctx, int(phantom_id), int(n_decays), int(seed),
+        None if opts is None else ctypes.byref(opts)))
+
+
+def nmd_reset_tallies(ctx, phantom_id):
+    _check(ctx, load_library().nmd_reset_tallies(ctx, int(phantom_id)))
+
+
+def nmd_get_dose(ctx, phantom_id, dose_rate, rel_uncertainty=None):
+    _check(ctx, load_library().nmd_get_dose(ctx, int(phantom_id), _dptr(dose_rate),
+                                            _dptr(rel_uncertainty)))
+
+
+def nmd_get_organ_dose(ctx, phantom_id, n_organs):
+    """Returns (Eq. 2 dose rate, Eq. 3 uncertainty, relative sigma of the
+    organ mean) as float64 numpy arrays of n_organs."""
+    r = np.zeros(n_organs)
+    e = np.zeros(n_organs)
+    s = np.zeros(n_organs)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    _check(ctx, load_library().nmd_get_organ_dose(ctx, int(phantom_id), int(n_organs), p(r),
+                                                  p(e), p(s)))
+    return r, e, s
+
+
+def nmd_get_organ_score(ctx, phantom_id, n_organs):
+    r = np.zeros(n_organs)
+    _check(ctx, load_library().nmd_get_organ_score(ctx, int(phantom_id), int(n_organs),
+                                                   r.ctypes.data_as(ctypes.c_void_p)))
+    return r
+
+
+def nmd_get_ledger(ctx, phantom_id) -> dict:
+    a = np.zeros(len(LEDGER_FIELDS))
+    _check(ctx, load_library().nmd_get_ledger(ctx, int(phantom_id),
+                                              a.ctypes.data_as(ctypes.c_void_p)))
+    return dict(zip(LEDGER_FIELDS, a.tolist()))
+
+
+def nmd_get_run_stats(ctx, phantom_id) -> dict:
+    a = np.zeros(len(STATS_FIELDS), dtype=np.uint64)
+    _check(ctx, load_library().nmd_get_run_stats(ctx, int(phantom_id),
+                                                 a.ctypes.data_as(ctypes.c_void_p)))
+    return dict(zip(STATS_FIELDS, [int(x) for x in a]))
+
+
+def nmd_get_tallies(ctx, phantom_id, sum_dev, sum2_dev):
+    n = ctypes.c_uint64()
+    _check(ctx, load_library().nmd_get_tallies(ctx, int(phantom_id), _dptr(sum_dev),
+                                               _dptr(sum2_dev), ctypes.byref(n)))
+    return int(n.value)
+
+
+def nmd_set_tallies(ctx, phantom_id, sum_dev, sum2_dev, n_decays):
+    _check(ctx, load_library().nmd_set_tallies(ctx, int(phantom_id), _dptr(sum_dev),
+                                               _dptr(sum2_dev), int(n_decays)))
+
+
+def nmd_debug_sample(ctx, kind, e_mev, n, seed, out):
+    _check(ctx, load_library().nmd_debug_sample(ctx, int(kind), float(e_mev), int(n), int(seed),
+                                                _dptr(out)))
+
+
+def nmd_debug_sample_source(ctx, phantom_id, n, seed, out):
+    _check(ctx, load_library().nmd_debug_sample_source(ctx, int(phantom_id), int(n), int(seed),
+                                                       _dptr(out)))
+
+
+def nmd_debug_xs(ctx, phantom_id, energies, out):
+    _check(ctx, load_library().nmd_debug_xs(ctx, int(phantom_id), int(energies.numel()),
+                                            _dptr(energies), _dptr(out)))
+
+
+# ---- convenience layer used by the tests and the benchmark ------------------
+class Engine:
+    """Owns one context and the device copies of the inputs handed to it."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the engine has no CPU path")
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.ctx = nmd_create(device, torch.cuda.current_stream(self.device))
+        self.problems = {}
+
+    def close(self):
+        if self.ctx is not None:
+            nmd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_problem(self, phantom_id, prob, with_activity=True):
+        t = self.torch
+        dev = self.device
+        rho = t.from_numpy(np.ascontiguousarray(prob.density, dtype=np.float32)).to(dev)
+        mat = t.from_numpy(np.ascontiguousarray(prob.material, dtype=np.uint8)).to(dev)
+        lab = t.from_numpy(np.ascontiguousarray(prob.label, dtype=np.uint8)).to(dev)
+        nmd_set_phantom(self.ctx, phantom_id, rho, mat, lab, prob.n_organs, prob.materials,
+                        prob.voxel_mm)
+        if with_activity:
+            act = t.from_numpy(np.ascontiguousarray(prob.activity, dtype=np.float32)).to(dev)
+            nmd_set_activity(self.ctx, phantom_id, act, prob.total_activity_bq)
+        self.problems[phantom_id] = prob
+
+    def run(self, phantom_id, n, seed, **kw):
+        o = nmd_run_opts_default()
+        for k, v in kw.items():
+            if k in ("pencil_origin_cm", "pencil_dir"):
+                for a in range(3):
+                    getattr(o, k)[a] = float(v[a])
+            elif k == "history_records":
+                o.history_records = None if v is None else v.data_ptr()
+            else:
+                setattr(o, k, v)
+        nmd_run_histories(self.ctx, phantom_id, n, seed, o)
+
+    def dose(self, phantom_id):
+        prob = self.problems[phantom_id]
+        rate = self.torch.empty(prob.shape, dtype=self.torch.float64, device=self.device)
+        rel = self.torch.empty_like(rate)
+        nmd_get_dose(self.ctx, phantom_id, rate, rel)
+        return rate, rel
+
+    def tallies(self, phantom_id):
+        prob = self.problems[phantom_id]
+        s = self.torch.empty(prob.shape, dtype=self.torch.float64, device=self.device)
+        s2 = self.torch.empty_like(s)
+        n = nmd_get_tallies(self.ctx, phantom_id, s, s2)
+        return s, s2, n
+
+    def organs(self, phantom_id):
+        return nmd_get_organ_dose(self.ctx, phantom_id, self.problems[phantom_id].n_organs)
+
+    def ledger(self, phantom_id):
+        return nmd_get_ledger(self.ctx, phantom_id)
+
+    def stats(self, phantom_id):
+        return nmd_get_run_stats(self.ctx, phantom_id)
+
+    def sync(self):
+        self.torch.cuda.synchronize(self.device)

@@ -1,0 +1,821 @@
+// Host engine and C ABI of the dosimetry library (see include/nmdose.h).
+//
+// The context owns: a (material, density) palette shared by its phantoms,
+// the Klein-Nishina table, per-phantom voxel records, organ labels, alias
+// tables, majorant tables and FP64 tallies, and the work-queue and
+// deposit-list scratch of the transport kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/nmdose.h"
+#include "nmd_internal.hpp"
+
+using namespace nmd;
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  template <class T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+struct Phantom {
+  int32_t nx = 0, ny = 0, nz = 0, n_org = 0;
+  double dx = 0, dy = 0, dz = 0;  // cm
+  uint64_t nvox = 0;
+  DevBuf rec, label, alias, tally, organ, ledger, stats, major, organ_w;
+  std::vector<int64_t> organ_count;  // voxels per label 0..n_org
+  std::vector<uint8_t> used;         // palette entries present
+  uint32_t n_alias = 0;
+  bool has_activity = false;
+  double a_ts = 0.0;
+  uint64_t n_done = 0;
+  double vkg() const { return dx * dy * dz * 1.0e-3; }  // kg per (g/cm^3)
+};
+
+struct PalEntry {
+  double z, zoa;
+  float rho;
+  float4 c;  // (cC, cPE, cR, rho)
+};
+
+}  // namespace
+
+struct nmd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<PalEntry> pal;
+  DevBuf d_pal, d_kn, d_queue, d_desc, d_dep_v, d_dep_e, d_acc;
+  uint32_t dep_lanes = 0;
+  int cu_count = 0;
+  float l2emin = 0, inv_dl2 = 0;
+  std::map<int, Phantom> ph;
+  bool poisoned = false;
+};
+
+namespace {
+
+nmd_status fail(nmd_ctx *c, nmd_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) {
+    c->err = buf;
+    if (s == NMD_E_HIP) c->poisoned = true;
+  }
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? NMD_E_OOM : NMD_E_HIP, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                 \
+  } while (0)
+
+nmd_status dev_alloc(nmd_ctx *c, DevBuf &b, size_t bytes) {
+  DevBuf nb;
+  if (bytes) {
+    hipError_t e = hipMalloc(&nb.p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, NMD_E_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    }
+    nb.n = bytes;
+  }
+  b = std::move(nb);
+  return NMD_OK;
+}
+
+// ---- model (host side of the device tables) --------------------------------
+double sigma_kn(double e) {
+  const double k = e / kMeC2;
+  const double a = 1.0 + 2.0 * k;
+  const double l = std::log(a);
+  return 2.0 * M_PI * kRe * kRe *
+         ((1.0 + k) / (k * k) * (2.0 * (1.0 + k) / a - l / k) + l / (2.0 * k) -
+          (1.0 + 3.0 * k) / (a * a));
+}
+double grid_e(int i) { return kEGridMin * std::pow(kEGridRatio, (double)i / (kNGrid - 1)); }
+
+// Coefficients of one (material, density) pair, FP64: mu_C = cC * N_A
+// sigma_KN(E), mu_PE = cPE / E^3, mu_R = cR / E^2 (cm^-1).
+void pal_coeffs(double z, double zoa, double rho, double &cc, double &cpe, double &cr) {
+  const double sref = sigma_kn(kERef);
+  const double a_pe = sref / (kZRef * kZRef * kZRef);
+  const double a_r = 0.1 * sref / kZRef;
+  cc = rho * zoa;
+  cpe = rho * kNA * zoa * a_pe * z * z * z * kERef * kERef * kERef;
+  cr = rho * kNA * zoa * a_r * z * kERef * kERef;
+}
+
+float round_up_f32(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+nmd_status sync(nmd_ctx *c) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return NMD_OK;
+}
+
+nmd_status check_ctx(nmd_ctx *c) {
+  if (!c) return NMD_E_INVALID;
+  if (c->poisoned) return fail(c, NMD_E_HIP, "context unusable after an earlier HIP error");
+  HIP_TRY(c, hipSetDevice(c->device));
+  return NMD_OK;
+}
+
+Phantom *find(nmd_ctx *c, int32_t id) {
+  auto it = c->ph.find(id);
+  return it == c->ph.end() ? nullptr : &it->second;
+}
+
+nmd_status upload_desc(nmd_ctx *c, int32_t id, Phantom &p) {
+  PhantomDesc d = {};
+  d.rec = p.rec.as<uint8_t>();
+  d.label = p.label.as<uint8_t>();
+  d.alias = p.alias.as<uint4>();
+  d.tally = p.tally.as<double2>();
+  d.organ = p.organ.as<double2>();
+  d.ledger = p.ledger.as<double>();
+  d.stats = p.stats.as<unsigned long long>();
+  d.ln2_major = p.major.as<float>();
+  d.organ_w = p.organ_w.as<double>();
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.nz = p.nz;
+  d.n_org = p.n_org;
+  d.fnx = (float)p.nx;
+  d.fny = (float)p.ny;
+  d.fnz = (float)p.nz;
+  d.dx = (float)p.dx;
+  d.dy = (float)p.dy;
+  d.dz = (float)p.dz;
+  d.inv_dx = (float)(1.0 / p.dx);
+  d.inv_dy = (float)(1.0 / p.dy);
+  d.inv_dz = (float)(1.0 / p.dz);
+  d.n_alias = p.n_alias;
+  d.pid = (uint32_t)id;
+  HIP_TRY(c, hipMemcpyAsync(c->d_desc.as<PhantomDesc>() + id, &d, sizeof d, hipMemcpyHostToDevice,
+                            c->stream));
+  return sync(c);
+}
+
+nmd_status zero_tallies(nmd_ctx *c, Phantom &p) {
+  HIP_TRY(c, launch_zero_bytes(p.tally.p, p.tally.n, c->stream));
+  HIP_TRY(c, launch_zero_bytes(p.organ.p, p.organ.n, c->stream));
+  HIP_TRY(c, launch_zero_bytes(p.ledger.p, p.ledger.n, c->stream));
+  HIP_TRY(c, launch_zero_bytes(p.stats.p, p.stats.n, c->stream));
+  p.n_done = 0;
+  return NMD_OK;
+}
+
+template <class T>
+nmd_status to_host(nmd_ctx *c, std::vector<T> &h, const T *src, uint64_t n) {
+  h.resize(n);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), src, n * sizeof(T), hipMemcpyDefault, c->stream));
+  return sync(c);
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+void nmd_run_opts_default(nmd_run_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->photons_per_decay = 2;
+  o->process_mask = 7;
+  o->max_real_events = 0;
+  o->photon_cutoff_mev = 0.010f;
+  o->source_kind = 0;
+  o->pencil_dir[0] = 1.0f;
+}
+
+nmd_status nmd_create(nmd_ctx **out, int device, void *stream) {
+  if (!out) return NMD_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return NMD_E_INVALID;
+  }
+  nmd_ctx *c = new nmd_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return NMD_E_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return NMD_E_HIP;
+  }
+  c->cu_count = prop.multiProcessorCount;
+  c->l2emin = (float)std::log2(kEGridMin);
+  c->inv_dl2 = (float)((kNGrid - 1) / std::log2(kEGridRatio));
+  std::vector<float> kn(kNGrid);
+  for (int i = 0; i < kNGrid; ++i) kn[i] = (float)std::log2(kNA * sigma_kn(grid_e(i)));
+  nmd_status s;
+  if ((s = dev_alloc(c, c->d_kn, kNGrid * sizeof(float))) ||
+      (s = dev_alloc(c, c->d_pal, kMaxPalette * sizeof(float4))) ||
+      (s = dev_alloc(c, c->d_queue, 2 * sizeof(unsigned long long))) ||
+      (s = dev_alloc(c, c->d_desc, kMaxPhantoms * sizeof(PhantomDesc))) ||
+      (s = dev_alloc(c, c->d_acc, kMaxOrganSlots * 2 * sizeof(double)))) {
+    delete c;
+    return s;
+  }
+  if (hipMemcpy(c->d_kn.p, kn.data(), kNGrid * sizeof(float), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    delete c;
+    return NMD_E_HIP;
+  }
+  *out = c;
+  return NMD_OK;
+}
+
+void nmd_destroy(nmd_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  delete c;
+}
+
+const char *nmd_last_error(const nmd_ctx *c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+nmd_status nmd_set_stream(nmd_ctx *c, void *stream) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  c->stream = (hipStream_t)stream;
+  return NMD_OK;
+}
+
+nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32_t nz, float dx_mm,
+                           float dy_mm, float dz_mm, const float *density, const uint8_t *material,
+                           const uint8_t *label, int32_t n_organs, const nmd_material *mats,
+                           int32_t n_mat) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  if (id < 0 || id >= kMaxPhantoms) return fail(c, NMD_E_INVALID, "phantom id %d out of 0..63", id);
+  if (nx < 1 || ny < 1 || nz < 1)
+    return fail(c, NMD_E_SHAPE, "dimensions must be >= 1 (%d, %d, %d)", nx, ny, nz);
+  const uint64_t nvox = (uint64_t)nx * ny * nz;
+  if (nvox >= (1ull << 31)) return fail(c, NMD_E_SHAPE, "nx*ny*nz must be < 2^31");
+  if (!(dx_mm > 0 && dy_mm > 0 && dz_mm > 0) || !std::isfinite(dx_mm) || !std::isfinite(dy_mm) ||
+      !std::isfinite(dz_mm))
+    return fail(c, NMD_E_INVALID, "voxel sizes must be finite and > 0");
+  if (!density || !material) return fail(c, NMD_E_INVALID, "density and material are required");
+  if (!mats || n_mat < 1 || n_mat > 8) return fail(c, NMD_E_INVALID, "n_materials must be 1..8");
+  if (n_organs < 0 || n_organs > 255) return fail(c, NMD_E_INVALID, "n_organs must be 0..255");
+  for (int m = 0; m < n_mat; ++m)
+    if (!(mats[m].z_eff > 0 && mats[m].z_eff < 200 && mats[m].z_over_a > 0 &&
+          mats[m].z_over_a <= 1.0))
+      return fail(c, NMD_E_INVALID, "material %d: need 0 < z_eff < 200 and 0 < Z/A <= 1", m);
+
+  std::vector<float> h_rho;
+  std::vector<uint8_t> h_mat, h_lab;
+  if ((s = to_host(c, h_rho, density, nvox)) || (s = to_host(c, h_mat, material, nvox))) return s;
+  if (label && (s = to_host(c, h_lab, label, nvox))) return s;
+
+  // palette (strong guarantee: work on a copy)
+  std::vector<PalEntry> pal = c->pal;
+  std::unordered_map<uint64_t, int> key_to_q;
+  std::vector<int> mat_pal_base(n_mat);
+  std::vector<uint8_t> rec(nvox);
+  std::vector<uint8_t> used(kMaxPalette, 0);
+  uint64_t last_key = ~0ull;
+  int last_q = 0;
+  for (uint64_t v = 0; v < nvox; ++v) {
+    const float r = h_rho[v];
+    const uint8_t m = h_mat[v];
+    if (!(r >= 1e-6f) || !std::isfinite(r))
+      return fail(c, NMD_E_INVALID, "density[%llu] = %g is not finite and >= 1e-6",
+                  (unsigned long long)v, (double)r);
+    if (m >= n_mat)
+      return fail(c, NMD_E_INVALID, "material[%llu] = %d >= n_materials", (unsigned long long)v, m);
+    uint32_t rb;
+    std::memcpy(&rb, &r, 4);
+    const uint64_t key = ((uint64_t)m << 32) | rb;
+    if (key != last_key) {
+      auto it = key_to_q.find(key);
+      if (it == key_to_q.end()) {
+        int q = -1;
+        for (size_t i = 0; i < pal.size(); ++i)
+          if (pal[i].z == mats[m].z_eff && pal[i].zoa == mats[m].z_over_a && pal[i].rho == r) {
+            q = (int)i;
+            break;
+          }
+        if (q < 0) {
+          if (pal.size() >= (size_t)kMaxPalette)
+            return fail(c, NMD_E_UNSUPPORTED,
+                        "more than %d distinct (material, density) pairs in this context",
+                        kMaxPalette);
+          PalEntry e;
+          e.z = mats[m].z_eff;
+          e.zoa = mats[m].z_over_a;
+          e.rho = r;
+          double cc, cpe, cr;
+          pal_coeffs(e.z, e.zoa, (double)r, cc, cpe, cr);
+          e.c = make_float4((float)cc, (float)cpe, (float)cr, r);
+          q = (int)pal.size();
+          pal.push_back(e);
+        }
+        it = key_to_q.emplace(key, q).first;
+      }
+      last_key = key;
+      last_q = it->second;
+    }
+    rec[v] = (uint8_t)last_q;
+    used[last_q] = 1;
+  }
+  std::vector<int64_t> count(n_organs + 1, 0);
+  if (label) {
+    for (uint64_t v = 0; v < nvox; ++v) {
+      if (h_lab[v] > n_organs)
+        return fail(c, NMD_E_INVALID, "organ_label[%llu] = %d > n_organs", (unsigned long long)v,
+                    h_lab[v]);
+      count[h_lab[v]]++;
+    }
+  }
+
+  Phantom p;
+  p.nx = nx;
+  p.ny = ny;
+  p.nz = nz;
+  p.n_org = n_organs;
+  p.dx = dx_mm / 10.0;
+  p.dy = dy_mm / 10.0;
+  p.dz = dz_mm / 10.0;
+  p.nvox = nvox;
+  p.organ_count = count;
+  p.used = used;
+
+  // majorant nodes: max over this phantom's pairs of the total attenuation
+  std::vector<float> maj(kNGrid);
+  for (int i = 0; i < kNGrid; ++i) {
+    const double e = grid_e(i);
+    const double s_na = kNA * sigma_kn(e);
+    double mx = 0.0;
+    for (size_t q = 0; q < pal.size(); ++q) {
+      if (!used[q]) continue;
+      double cc, cpe, cr;
+      pal_coeffs(pal[q].z, pal[q].zoa, (double)pal[q].rho, cc, cpe, cr);
+      const double mu = cc * s_na + cpe / (e * e * e) + cr / (e * e);
+      mx = std::max(mx, mu);
+    }
+    maj[i] = round_up_f32(std::log2(mx));
+  }
+  std::vector<double> ow(n_organs + 1, 0.0);
+  for (int o = 0; o <= n_organs; ++o)
+    ow[o] = count[o] > 0 ? kJPerMeV / (p.vkg() * (double)count[o]) : 0.0;
+
+  if ((s = dev_alloc(c, p.rec, nvox)) || (s = dev_alloc(c, p.tally, nvox * sizeof(double2))) ||
+      (s = dev_alloc(c, p.organ, (n_organs + 1) * sizeof(double2))) ||
+      (s = dev_alloc(c, p.ledger, 8 * sizeof(double))) ||
+      (s = dev_alloc(c, p.stats, 16 * sizeof(unsigned long long))) ||
+      (s = dev_alloc(c, p.major, kNGrid * sizeof(float))) ||
+      (s = dev_alloc(c, p.organ_w, (n_organs + 1) * sizeof(double))))
+    return s;
+  if (label && (s = dev_alloc(c, p.label, nvox))) return s;
+  HIP_TRY(c, hipMemcpyAsync(p.rec.p, rec.data(), nvox, hipMemcpyHostToDevice, c->stream));
+  if (label)
+    HIP_TRY(c, hipMemcpyAsync(p.label.p, h_lab.data(), nvox, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p.major.p, maj.data(), kNGrid * sizeof(float), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p.organ_w.p, ow.data(), ow.size() * sizeof(double),
+                            hipMemcpyHostToDevice, c->stream));
+  std::vector<float4> pal_dev(pal.size());
+  for (size_t i = 0; i < pal.size(); ++i) pal_dev[i] = pal[i].c;
+  HIP_TRY(c, hipMemcpyAsync(c->d_pal.p, pal_dev.data(), pal_dev.size() * sizeof(float4),
+                            hipMemcpyHostToDevice, c->stream));
+  if ((s = zero_tallies(c, p))) return s;
+  if ((s = sync(c))) return s;
+  c->pal = pal;
+  c->ph[id] = std::move(p);
+  return upload_desc(c, id, c->ph[id]);
+}
+
+nmd_status nmd_set_activity(nmd_ctx *c, int32_t id, const float *act, double total_bq) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!act) return fail(c, NMD_E_INVALID, "activity is required");
+  std::vector<float> a;
+  if ((s = to_host(c, a, act, p->nvox))) return s;
+  double sum = 0.0;
+  std::vector<uint32_t> nz;
+  for (uint64_t v = 0; v < p->nvox; ++v) {
+    const float x = a[v];
+    if (!(x >= 0.0f) || !std::isfinite(x))
+      return fail(c, NMD_E_INVALID, "activity[%llu] = %g is not finite and >= 0",
+                  (unsigned long long)v, (double)x);
+    if (x > 0.0f) {
+      nz.push_back((uint32_t)v);
+      sum += x;
+    }
+  }
+  if (!(sum > 0.0)) return fail(c, NMD_E_INVALID, "activity map is all zero");
+  // Vose's alias table over the voxels with activity, in FP64.
+  const size_t n = nz.size();
+  std::vector<double> q(n);
+  for (size_t i = 0; i < n; ++i) q[i] = (double)a[nz[i]] * (double)n / sum;
+  std::vector<uint32_t> small, large;
+  small.reserve(n);
+  large.reserve(n);
+  for (size_t i = 0; i < n; ++i) (q[i] < 1.0 ? small : large).push_back((uint32_t)i);
+  std::vector<double> prob(n, 1.0);
+  std::vector<uint32_t> alias(n);
+  for (size_t i = 0; i < n; ++i) alias[i] = (uint32_t)i;
+  while (!small.empty() && !large.empty()) {
+    const uint32_t l = small.back();
+    small.pop_back();
+    const uint32_t g = large.back();
+    prob[l] = q[l];
+    alias[l] = g;
+    q[g] = (q[g] + q[l]) - 1.0;
+    if (q[g] < 1.0) {
+      large.pop_back();
+      small.push_back(g);
+    }
+  }
+  // leftovers are 1 up to rounding
+  std::vector<uint4> tab(n);
+  for (size_t i = 0; i < n; ++i) {
+    float pr = (float)prob[i];
+    uint32_t pb;
+    std::memcpy(&pb, &pr, 4);
+    tab[i] = make_uint4(pb, nz[i], nz[alias[i]], 0u);
+  }
+  DevBuf d;
+  if ((s = dev_alloc(c, d, n * sizeof(uint4)))) return s;
+  HIP_TRY(c, hipMemcpyAsync(d.p, tab.data(), n * sizeof(uint4), hipMemcpyHostToDevice, c->stream));
+  if ((s = sync(c))) return s;
+  p->alias = std::move(d);
+  p->n_alias = (uint32_t)n;
+  p->has_activity = true;
+  p->a_ts = total_bq > 0.0 ? total_bq : sum * (p->dx * p->dy * p->dz);
+  if ((s = zero_tallies(c, *p))) return s;
+  return upload_desc(c, id, *p);
+}
+
+nmd_status nmd_reset_tallies(nmd_ctx *c, int32_t id) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  if (id == -1) {
+    for (auto &kv : c->ph)
+      if ((s = zero_tallies(c, kv.second))) return s;
+    return NMD_OK;
+  }
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  return zero_tallies(c, *p);
+}
+
+nmd_status nmd_run_histories(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
+                             const nmd_run_opts *opts_in) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  nmd_run_opts o;
+  if (opts_in)
+    o = *opts_in;
+  else
+    nmd_run_opts_default(&o);
+  if (o.photons_per_decay < 1 || o.photons_per_decay > 2)
+    return fail(c, NMD_E_INVALID, "photons_per_decay must be 1 or 2");
+  if (o.process_mask > 7) return fail(c, NMD_E_INVALID, "process_mask must be <= 7");
+  if (!(o.photon_cutoff_mev >= 0.001f && o.photon_cutoff_mev <= 0.511f))
+    return fail(c, NMD_E_INVALID, "photon cutoff must lie in [0.001, 0.511] MeV");
+  if (o.source_kind > 1) return fail(c, NMD_E_INVALID, "source_kind must be 0 or 1");
+  float pd[3] = {o.pencil_dir[0], o.pencil_dir[1], o.pencil_dir[2]};
+  if (o.source_kind == 1) {
+    const double nn = std::sqrt((double)pd[0] * pd[0] + (double)pd[1] * pd[1] + (double)pd[2] * pd[2]);
+    if (!(nn > 0) || !std::isfinite(nn)) return fail(c, NMD_E_INVALID, "pencil_dir must be nonzero");
+    for (int a = 0; a < 3; ++a) pd[a] = (float)(pd[a] / nn);
+    if (o.history_records && id == -1)
+      return fail(c, NMD_E_INVALID, "history_records needs a single phantom");
+  }
+  if (n == 0) return NMD_OK;
+
+  std::vector<int32_t> ids;
+  if (id == -1) {
+    for (auto &kv : c->ph)
+      if (kv.second.has_activity || o.source_kind == 1) ids.push_back(kv.first);
+    if (ids.empty()) return fail(c, NMD_E_STATE, "no phantom has an activity map");
+    if (o.history_records) return fail(c, NMD_E_INVALID, "history_records needs a single phantom");
+  } else {
+    Phantom *p = find(c, id);
+    if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+    if (o.source_kind == 0 && !p->has_activity)
+      return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
+    ids.push_back(id);
+  }
+  if (o.source_kind == 1) {
+    for (int32_t i : ids) {
+      const Phantom &p = c->ph[i];
+      const double L[3] = {p.nx * p.dx, p.ny * p.dy, p.nz * p.dz};
+      for (int a = 0; a < 3; ++a)
+        if (!(o.pencil_origin_cm[a] >= 0.0f && o.pencil_origin_cm[a] < L[a]))
+          return fail(c, NMD_E_INVALID, "pencil origin must lie inside the grid");
+    }
+  }
+
+  // launch shape
+  const int per_cu = transport_occupancy_blocks_per_cu(o.history_records != nullptr);
+  uint32_t grid = o.grid_blocks ? o.grid_blocks : (uint32_t)(c->cu_count * per_cu);
+  grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, 65536));
+  const uint32_t lanes = grid * kBlock;
+  if (lanes > c->dep_lanes) {
+    if ((s = dev_alloc(c, c->d_dep_v, (size_t)lanes * kDepCap * sizeof(uint32_t))) ||
+        (s = dev_alloc(c, c->d_dep_e, (size_t)lanes * kDepCap * sizeof(double)))) {
+      c->dep_lanes = 0;
+      return s;
+    }
+    c->dep_lanes = lanes;
+  }
+  uint32_t chunk = o.chunk;
+  if (chunk == 0) {
+    // enough claims per wave to balance, few enough to keep the queue cold
+    const uint64_t waves = (uint64_t)grid * kWavesPerBlock;
+    uint64_t ch = n * ids.size() / (waves * 16);
+    ch = std::max<uint64_t>(64, std::min<uint64_t>(ch, 4096));
+    chunk = (uint32_t)ch;
+  }
+
+  RunParams rp = {};
+  rp.desc = c->d_desc.as<PhantomDesc>();
+  rp.n_ph = (int32_t)ids.size();
+  rp.chunk = chunk;
+  uint64_t total = 0;
+  for (size_t i = 0; i < ids.size(); ++i) {
+    Phantom &p = c->ph[ids[i]];
+    rp.slot[i].hid0 = p.n_done;
+    rp.slot[i].n_hist = n;
+    rp.slot[i].chunk0 = total;
+    rp.slot[i].id = ids[i];
+    total += (n + chunk - 1) / chunk;
+  }
+  rp.total_chunks = total;
+  rp.queue = c->d_queue.as<unsigned long long>();
+  rp.abort_after = o.abort_after_chunks;
+  rp.seed_lo = (uint32_t)seed;
+  rp.seed_hi = (uint32_t)(seed >> 32);
+  rp.nph = o.source_kind == 1 ? 1u : o.photons_per_decay;
+  rp.mask = o.process_mask;
+  rp.max_real = o.max_real_events;
+  rp.cutoff = o.photon_cutoff_mev;
+  rp.source_kind = o.source_kind;
+  for (int a = 0; a < 3; ++a) {
+    rp.po[a] = o.pencil_origin_cm[a];
+    rp.pd[a] = pd[a];
+  }
+  rp.palette = c->d_pal.as<float4>();
+  rp.n_pal = (int32_t)c->pal.size();
+  rp.ln2_kn = c->d_kn.as<float>();
+  rp.l2emin = c->l2emin;
+  rp.inv_dl2 = c->inv_dl2;
+  rp.dep_v = c->d_dep_v.as<uint32_t>();
+  rp.dep_e = c->d_dep_e.as<double>();
+  rp.n_lanes = lanes;
+  rp.hist_rec = o.history_records;
+
+  HIP_TRY(c, launch_zero_bytes(c->d_queue.p, c->d_queue.n, c->stream));
+  HIP_TRY(c, launch_transport(rp, (int)grid, o.history_records != nullptr, c->stream));
+  for (int32_t i : ids) c->ph[i].n_done += n;
+  if (o.abort_after_chunks) {
+    unsigned long long q[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(q, c->d_queue.p, sizeof q, hipMemcpyDeviceToHost, c->stream));
+    if ((s = sync(c))) return s;
+    if (q[1]) return fail(c, NMD_E_ABORTED, "run stopped by the abort hook");
+  }
+  return NMD_OK;
+}
+
+nmd_status nmd_get_dose(nmd_ctx *c, int32_t id, double *rate, double *rel) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->has_activity || p->n_done == 0)
+    return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
+  if (!rate) return fail(c, NMD_E_INVALID, "dose_rate buffer is required");
+  HIP_TRY(c, launch_finalize(p->rec.as<uint8_t>(), c->d_pal.as<float4>(), p->tally.as<double2>(),
+                             p->nvox, (double)p->n_done, p->vkg(), p->a_ts, rate, rel, c->stream));
+  return NMD_OK;
+}
+
+nmd_status nmd_get_organ_dose(nmd_ctx *c, int32_t id, int32_t n_organs, double *rate,
+                              double *eps3, double *sig_mean) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->label.p) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
+  if (!p->has_activity || p->n_done == 0)
+    return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
+  if (n_organs < 0 || n_organs > p->n_org)
+    return fail(c, NMD_E_INVALID, "n_organs %d exceeds the phantom's %d", n_organs, p->n_org);
+  const double n = (double)p->n_done;
+  if (rate || eps3) {
+    HIP_TRY(c, launch_zero_bytes(c->d_acc.p, (p->n_org + 1) * 2 * sizeof(double), c->stream));
+    HIP_TRY(c, launch_organ_reduce(p->rec.as<uint8_t>(), p->label.as<uint8_t>(),
+                                   c->d_pal.as<float4>(), p->tally.as<double2>(), p->nvox,
+                                   p->n_org, n, p->vkg(), p->a_ts, c->d_acc.as<double>(),
+                                   c->stream));
+    std::vector<double> acc((p->n_org + 1) * 2);
+    HIP_TRY(c, hipMemcpyAsync(acc.data(), c->d_acc.p, acc.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    if ((s = sync(c))) return s;
+    for (int o = 1; o <= n_organs; ++o) {
+      const double cnt = (double)p->organ_count[o];
+      if (rate) rate[o - 1] = cnt > 0 ? acc[2 * o] / cnt : 0.0;
+      if (eps3) eps3[o - 1] = cnt > 0 ? std::sqrt(acc[2 * o + 1] / cnt) : 0.0;
+    }
+  }
+  if (sig_mean) {
+    std::vector<double2> org(p->n_org + 1);
+    HIP_TRY(c, hipMemcpyAsync(org.data(), p->organ.p, org.size() * sizeof(double2),
+                              hipMemcpyDeviceToHost, c->stream));
+    if ((s = sync(c))) return s;
+    for (int o = 1; o <= n_organs; ++o) {
+      const double m = org[o].x / n;
+      double var = n > 1 ? (org[o].y / n - m * m) / (n - 1.0) : 0.0;
+      if (var < 0) var = 0;
+      sig_mean[o - 1] = m > 0 ? std::sqrt(var) / m : 0.0;
+    }
+  }
+  return NMD_OK;
+}
+
+nmd_status nmd_get_organ_score(nmd_ctx *c, int32_t id, int32_t n_organs, double *rate) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->label.p) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
+  if (n_organs < 0 || n_organs > p->n_org || !rate)
+    return fail(c, NMD_E_INVALID, "bad n_organs or output");
+  if (p->n_done == 0) return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
+  std::vector<double2> org(p->n_org + 1);
+  HIP_TRY(c, hipMemcpyAsync(org.data(), p->organ.p, org.size() * sizeof(double2),
+                            hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c))) return s;
+  for (int o = 1; o <= n_organs; ++o) rate[o - 1] = p->a_ts * org[o].x / (double)p->n_done;
+  return NMD_OK;
+}
+
+nmd_status nmd_get_ledger(nmd_ctx *c, int32_t id, double *ledger) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!ledger) return fail(c, NMD_E_INVALID, "ledger output is required");
+  double l[8];
+  unsigned long long st[16];
+  HIP_TRY(c, hipMemcpyAsync(l, p->ledger.p, sizeof l, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(st, p->stats.p, sizeof st, hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c))) return s;
+  ledger[0] = (double)st[NMD_STAT_PHOTONS] * (double)kE0;
+  for (int i = 1; i < NMD_LEDGER_N; ++i) ledger[i] = l[i];
+  return NMD_OK;
+}
+
+nmd_status nmd_get_run_stats(nmd_ctx *c, int32_t id, uint64_t *stats) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!stats) return fail(c, NMD_E_INVALID, "stats output is required");
+  unsigned long long st[16];
+  HIP_TRY(c, hipMemcpyAsync(st, p->stats.p, sizeof st, hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c))) return s;
+  for (int i = 0; i < NMD_STAT_N; ++i) stats[i] = st[i];
+  return NMD_OK;
+}
+
+nmd_status nmd_get_tallies(nmd_ctx *c, int32_t id, double *sum, double *sum2, uint64_t *n) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (n) *n = p->n_done;
+  if (sum)
+    HIP_TRY(c, hipMemcpy2DAsync(sum, sizeof(double), p->tally.p, sizeof(double2), sizeof(double),
+                                p->nvox, hipMemcpyDeviceToDevice, c->stream));
+  if (sum2)
+    HIP_TRY(c, hipMemcpy2DAsync(sum2, sizeof(double), p->tally.as<char>() + sizeof(double),
+                                sizeof(double2), sizeof(double), p->nvox,
+                                hipMemcpyDeviceToDevice, c->stream));
+  return NMD_OK;
+}
+
+nmd_status nmd_set_tallies(nmd_ctx *c, int32_t id, const double *sum, const double *sum2,
+                           uint64_t n) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->has_activity) return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
+  if (!sum || !sum2) return fail(c, NMD_E_INVALID, "both sums are required");
+  if ((s = zero_tallies(c, *p))) return s;
+  HIP_TRY(c, hipMemcpy2DAsync(p->tally.p, sizeof(double2), sum, sizeof(double), sizeof(double),
+                              p->nvox, hipMemcpyDefault, c->stream));
+  HIP_TRY(c, hipMemcpy2DAsync(p->tally.as<char>() + sizeof(double), sizeof(double2), sum2,
+                              sizeof(double), sizeof(double), p->nvox, hipMemcpyDefault,
+                              c->stream));
+  p->n_done = n;
+  return sync(c);
+}
+
+nmd_status nmd_debug_sample(nmd_ctx *c, int32_t kind, double e_mev, uint64_t n, uint64_t seed,
+                            double *out) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  if (!(kind == 0 || kind == 1 || kind == 2 || kind == 3 || kind == 5))
+    return fail(c, NMD_E_INVALID, "unknown sample kind %d", kind);
+  if (kind == 3 && !(e_mev >= 0.001 && e_mev <= 0.511))
+    return fail(c, NMD_E_INVALID, "energy must lie in [0.001, 0.511] MeV");
+  if (!out && n) return fail(c, NMD_E_INVALID, "output is required");
+  HIP_TRY(c, launch_debug_sample(kind, (float)e_mev, n, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                 out, c->stream));
+  return NMD_OK;
+}
+
+nmd_status nmd_debug_sample_source(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
+                                   uint32_t *out) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p || !p->has_activity) return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
+  if (!out && n) return fail(c, NMD_E_INVALID, "output is required");
+  HIP_TRY(c, launch_debug_source(p->alias.as<uint4>(), p->n_alias, (uint32_t)id, n, (uint32_t)seed,
+                                 (uint32_t)(seed >> 32), out, c->stream));
+  return NMD_OK;
+}
+
+nmd_status nmd_debug_xs(nmd_ctx *c, int32_t id, uint64_t n, const float *energies, float *out) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if ((!energies || !out) && n) return fail(c, NMD_E_INVALID, "buffers are required");
+  DevBuf used;
+  if ((s = dev_alloc(c, used, kMaxPalette))) return s;
+  HIP_TRY(c, hipMemcpyAsync(used.p, p->used.data(), kMaxPalette, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_debug_xs(c->d_pal.as<float4>(), used.as<uint8_t>(), (int)c->pal.size(),
+                             c->d_kn.as<float>(), p->major.as<float>(), n, energies, out,
+                             c->l2emin, c->inv_dl2, c->stream));
+  return sync(c);  // `used` is freed on return
+}
+
+}  // extern "C"

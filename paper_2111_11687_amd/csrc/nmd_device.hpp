@@ -1,0 +1,178 @@
+// Device-side building blocks of the transport kernel: the counter-based
+// random stream, the samplers and the direction rotation, all in FP32.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nmd_internal.hpp"
+
+namespace nmd {
+
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with a Weyl-sequence key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t &o0,
+                                              uint32_t &o1, uint32_t &o2, uint32_t &o3) {
+#pragma unroll 1
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  o0 = c0;
+  o1 = c1;
+  o2 = c2;
+  o3 = c3;
+}
+
+// Random stream of one history: counter (block, hid_lo, hid_hi, phantom),
+// key (seed_lo, seed_hi); the four words of a block are handed out in order.
+template <bool kCount>
+struct Stream {
+  uint32_t k0, k1, h0, h1, pid, blk;
+  uint32_t b0, b1, b2, b3;
+  uint32_t pos;
+  uint32_t n_drawn;  // uniforms handed out (debug records only)
+
+  __device__ __forceinline__ void init(uint32_t seed_lo, uint32_t seed_hi, unsigned long long hid,
+                                       uint32_t p) {
+    k0 = seed_lo;
+    k1 = seed_hi;
+    h0 = (uint32_t)hid;
+    h1 = (uint32_t)(hid >> 32);
+    pid = p;
+    blk = 0;
+    pos = 4;
+    n_drawn = 0;
+  }
+  __device__ __forceinline__ uint32_t word() {
+    if (pos == 4) {
+      philox4x32_10(blk, h0, h1, pid, k0, k1, b0, b1, b2, b3);
+      ++blk;
+      pos = 0;
+    }
+    const uint32_t x = pos == 0 ? b0 : (pos == 1 ? b1 : (pos == 2 ? b2 : b3));
+    ++pos;
+    if (kCount) ++n_drawn;
+    return x;
+  }
+  // ((x >> 9) + 1/2) * 2^-23: exactly representable, strictly inside (0, 1).
+  __device__ __forceinline__ float uniform() {
+    return ((float)(word() >> 9) + 0.5f) * (1.0f / 8388608.0f);
+  }
+};
+
+// Isotropic direction, Marsaglia (1972).
+template <class S>
+__device__ __forceinline__ void marsaglia(S &st, float &dx, float &dy, float &dz) {
+  float v1, v2, s;
+  do {
+    v1 = 2.0f * st.uniform() - 1.0f;
+    v2 = 2.0f * st.uniform() - 1.0f;
+    s = v1 * v1 + v2 * v2;
+  } while (s >= 1.0f);
+  const float q = 2.0f * __builtin_sqrtf(1.0f - s);
+  dx = v1 * q;
+  dy = v2 * q;
+  dz = 1.0f - 2.0f * s;
+}
+
+// Klein-Nishina energy ratio eps = E'/E and cos(theta) by the Butcher-Messel
+// composition-rejection: the eps density (1/eps + eps) g(eps) on [eps0, 1]
+// is split into the exactly sampled 1/eps and eps parts, weighted by
+// ln(1/eps0) and (1 - eps0^2)/2, and thinned by g = 1 - eps sin^2/(1+eps^2).
+template <class S>
+__device__ __forceinline__ float klein_nishina(S &st, float k, float &cost) {
+  const float a = 1.0f + 2.0f * k;
+  const float eps0 = 1.0f / a;
+  const float e02 = eps0 * eps0;
+  const float a1 = fast_log2(a) * 0.69314718055994531f;  // ln(1 + 2k)
+  const float a2 = 0.5f * (1.0f - e02);
+  const float inv_k = 1.0f / k;
+  float eps, t;
+  for (;;) {
+    const float r1 = st.uniform();
+    const float r2 = st.uniform();
+    const float r3 = st.uniform();
+    if (r1 * (a1 + a2) < a1)
+      eps = fast_exp2(-a1 * r2 * 1.4426950408889634f);
+    else
+      eps = __builtin_sqrtf(e02 + (1.0f - e02) * r2);
+    t = (1.0f - eps) * inv_k / eps;
+    const float sin2 = t * (2.0f - t);
+    const float g = 1.0f - eps * sin2 / (1.0f + eps * eps);
+    if (r3 < g) break;
+  }
+  cost = 1.0f - t;
+  return eps;
+}
+
+// Thomson polar angle: invert the CDF (c^3 + 3c + 4)/8 with Cardano's root
+// c = w - 1/w, w = cbrt(a + sqrt(a^2 + 1)), a = 4u - 2; the odd symmetry in
+// a keeps the cancellation away.
+__device__ __forceinline__ float thomson(float u) {
+  const float a = 4.0f * u - 2.0f;
+  const float aa = fabsf(a);
+  const float w = cbrtf(aa + __builtin_sqrtf(aa * aa + 1.0f));
+  return copysignf(w - 1.0f / w, a);
+}
+
+// Rotate (ux,uy,uz) by polar cos(theta) and azimuth 2 pi uphi about the
+// orthonormal basis of Duff et al. (JCGT 2017): no pole special case and no
+// loss of precision near the z axis in FP32.
+__device__ __forceinline__ void rotate(float &ux, float &uy, float &uz, float cost, float uphi) {
+  const float sint = __builtin_sqrtf(fmaxf(0.0f, 1.0f - cost * cost));
+  const float cphi = __builtin_amdgcn_cosf(uphi);  // argument in revolutions
+  const float sphi = __builtin_amdgcn_sinf(uphi);
+  const float sg = uz >= 0.0f ? 1.0f : -1.0f;
+  const float a = -1.0f / (sg + uz);
+  const float b = ux * uy * a;
+  const float sc = sint * cphi, ss = sint * sphi;
+  const float nu = cost * ux + sc * (1.0f + sg * ux * ux * a) + ss * b;
+  const float nv = cost * uy + sc * (sg * b) + ss * (sg + uy * uy * a);
+  const float nw = cost * uz - sc * (sg * ux) - ss * uy;
+  const float n = __builtin_amdgcn_rsqf(nu * nu + nv * nv + nw * nw);
+  ux = nu * n;
+  uy = nv * n;
+  uz = nw * n;
+}
+
+// Energy-dependent factors: mu_C = cC * sig, mu_PE = cPE * gpe, mu_R = cR * gr
+// and the majorant.  sig and the majorant are log-log interpolated on the
+// 256-node grid; the photoelectric and Rayleigh power laws are exact.
+struct EnergyParams {
+  float sig, gpe, gr, mu_hat, inv_mu_ln2;
+};
+
+__device__ __forceinline__ EnergyParams energy_params(float E, const float *__restrict__ ln2_kn,
+                                                      const float *__restrict__ ln2_maj,
+                                                      float l2emin, float inv_dl2) {
+  EnergyParams p;
+  const float t = (fast_log2(E) - l2emin) * inv_dl2;
+  int i = (int)floorf(t);
+  i = i < 0 ? 0 : (i > kNGrid - 2 ? kNGrid - 2 : i);
+  const float f = t - (float)i;
+  const float k0 = ln2_kn[i], k1 = ln2_kn[i + 1];
+  const float m0 = ln2_maj[i], m1 = ln2_maj[i + 1];
+  p.sig = fast_exp2(k0 + f * (k1 - k0));
+  p.mu_hat = kKappa * fast_exp2(m0 + f * (m1 - m0));
+  p.inv_mu_ln2 = 0.69314718055994531f / p.mu_hat;
+  const float ie = 1.0f / E;
+  p.gr = ie * ie;
+  p.gpe = p.gr * ie;
+  return p;
+}
+
+}  // namespace nmd

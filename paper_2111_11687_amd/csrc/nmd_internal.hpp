@@ -1,0 +1,104 @@
+// Internal interface between the host engine (nmd_api.hip) and the device
+// kernels (nmd_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nmd {
+
+constexpr int kMaxPhantoms = 64;
+constexpr int kMaxPalette = 256;        // u8 voxel records
+constexpr int kNGrid = 256;             // energy nodes, 1 keV .. 511 keV
+constexpr int kDepCap = 64;             // distinct deposit voxels kept per history
+constexpr int kBlock = 256;             // transport workgroup size (4 waves)
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kMaxOrganSlots = 256;     // labels 0..255
+constexpr int kRecN = 10;               // per-history debug record width
+constexpr int kStatN = 14;
+constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
+
+// Model constants.
+constexpr double kMeC2 = 0.51099895;            // MeV
+constexpr double kNA = 6.02214076e23;
+constexpr double kRe = 2.8179403262e-13;        // cm
+constexpr double kJPerMeV = 1.602176634e-13;
+constexpr double kERef = 0.030;                 // MeV, cross-section anchor
+constexpr double kZRef = 7.4;
+constexpr double kEGridMin = 1.0e-3;            // MeV
+constexpr double kEGridRatio = 511.0;
+constexpr float kE0 = 0.511f;                   // annihilation photon energy
+constexpr float kKappa = 1.0f + 1.0f / 16384.0f;  // majorant inflation
+
+// Static per-phantom descriptor (device array indexed by phantom id).
+struct PhantomDesc {
+  const uint8_t *rec;        // palette index per voxel
+  const uint8_t *label;      // organ label per voxel, or nullptr
+  const uint4 *alias;        // {prob bits, voxel, alias voxel, 0}
+  double2 *tally;            // (S, S2) per voxel
+  double2 *organ;            // (O, O2) per label slot
+  double *ledger;            // [6]
+  unsigned long long *stats; // [kStatN]
+  const float *ln2_major;    // [kNGrid] log2 of majorant nodes, cm^-1
+  const double *organ_w;     // [n_org+1] c / (V[cm^3] 1e-3 N_o), J/MeV per kg*(g/cm^3)
+  int32_t nx, ny, nz, n_org;
+  float fnx, fny, fnz;
+  float dx, dy, dz, inv_dx, inv_dy, inv_dz;
+  uint32_t n_alias;
+  uint32_t pid;
+};
+
+// Per-run fields of one phantom of a launch.
+struct RunSlot {
+  unsigned long long hid0;    // first history id of this run
+  unsigned long long n_hist;  // histories in this run
+  unsigned long long chunk0;  // first work-queue chunk of this phantom
+  int32_t id;                 // index into the descriptor array
+  int32_t pad;
+};
+
+struct RunParams {
+  const PhantomDesc *desc;   // device [kMaxPhantoms]
+  int32_t n_ph;
+  uint32_t chunk;
+  unsigned long long total_chunks;
+  unsigned long long *queue; // [0] claim counter, [1] abort flag
+  unsigned long long abort_after;
+  uint32_t seed_lo, seed_hi;
+  uint32_t nph;              // photons per decay
+  uint32_t mask;
+  uint32_t max_real;
+  float cutoff;
+  uint32_t source_kind;
+  float po[3], pd[3];
+  const float4 *palette;     // [n_pal] (cC, cPE, cR, rho)
+  int32_t n_pal;
+  const float *ln2_kn;       // [kNGrid] log2(N_A sigma_KN(E_i))
+  float l2emin, inv_dl2;     // grid coordinate t = (log2 E - l2emin) * inv_dl2
+  uint32_t *dep_v;           // [kDepCap][n_lanes]
+  double *dep_e;             // [kDepCap][n_lanes]
+  uint32_t n_lanes;
+  double *hist_rec;          // debug [n_hist][kRecN] or nullptr
+  RunSlot slot[kMaxPhantoms];
+};
+
+hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_t s);
+int transport_occupancy_blocks_per_cu(bool debug);
+hipError_t launch_finalize(const uint8_t *rec, const float4 *palette, const double2 *tally,
+                           uint64_t nvox, double n_decays, double voxel_kg_per_rho,
+                           double a_ts, double *rate, double *rel, hipStream_t s);
+hipError_t launch_organ_reduce(const uint8_t *rec, const uint8_t *label, const float4 *palette,
+                               const double2 *tally, uint64_t nvox, int n_org, double n_decays,
+                               double voxel_kg_per_rho, double a_ts,
+                               double *acc /* [(n_org+1)*2] */, hipStream_t s);
+hipError_t launch_debug_sample(int kind, float e_mev, uint64_t n, uint32_t seed_lo,
+                               uint32_t seed_hi, double *out, hipStream_t s);
+hipError_t launch_debug_source(const uint4 *alias, uint32_t n_alias, uint32_t pid, uint64_t n,
+                               uint32_t seed_lo, uint32_t seed_hi, uint32_t *out,
+                               hipStream_t s);
+hipError_t launch_debug_xs(const float4 *palette, const uint8_t *used, int n_pal,
+                           const float *ln2_kn, const float *ln2_major, uint64_t n,
+                           const float *energies, float *out, float l2emin, float inv_dl2,
+                           hipStream_t s);
+hipError_t launch_zero_bytes(void *p, uint64_t nbytes, hipStream_t s);
+
+}  // namespace nmd

@@ -1,0 +1,661 @@
+// Device kernels of the dosimetry engine (gfx950, wave64).
+//
+//   transport_kernel  persistent Woodcock photon transport with a work queue,
+//                     lane regeneration and history-by-history scoring
+//   finalize_kernel   dose-rate and relative-uncertainty maps (Eq. 1)
+//   organ_kernel      segmented per-organ reduction (Eq. 2, Eq. 3)
+//   debug kernels     sampler dumps and cross-section probes for the tests
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nmd_device.hpp"
+#include "nmd_internal.hpp"
+
+namespace nmd {
+
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t rank_in(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Transport
+// ---------------------------------------------------------------------------
+
+// Per-wave accumulators in LDS, flushed to the phantom's globals when the
+// wave changes phantom or exits.  Ledger slots follow NMD_LEDGER_* (slot 0,
+// emitted, is derived from the photon count on the host); counters follow
+// NMD_STAT_*.
+struct WaveAcc {
+  double ledger[6];
+  unsigned long long stat[kStatN];
+};
+
+template <bool kDebug>
+__global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
+  __shared__ float4 s_pal[kMaxPalette];
+  __shared__ double2 s_org[kWavesPerBlock][kMaxOrganSlots];
+  __shared__ WaveAcc s_acc[kWavesPerBlock];
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave = tid >> 6;
+  const uint32_t lane = lane_id();
+  const uint32_t gl = blockIdx.x * kBlock + tid;  // lane slot in the deposit lists
+  const uint32_t L = P.n_lanes;
+  WaveAcc &wa = s_acc[wave];
+
+  for (int i = tid; i < P.n_pal; i += kBlock) s_pal[i] = P.palette[i];
+  for (int i = lane; i < kMaxOrganSlots; i += 64) s_org[wave][i] = make_double2(0.0, 0.0);
+  if (lane < 6) wa.ledger[lane] = 0.0;
+  if (lane < kStatN) wa.stat[lane] = 0ull;
+  __syncthreads();
+
+  Stream<kDebug> st;
+
+  // lane state
+  bool alive = false;
+  float px = 0, py = 0, pz = 0, ux = 0, uy = 0, uz = 0, E = 0;
+  float ox = 0, oy = 0, oz = 0, dx0 = 0, dy0 = 0, dz0 = 0;
+  uint32_t photon = 0, n_real = 0, cnt = 0, psteps = 0;
+  uint32_t h_steps = 0, h_nulls = 0, h_cr = 0, h_pe_esc = 0;  // per-history counts
+  EnergyParams ep = {};
+  unsigned long long run_rel = 0;
+  double h_esc = 0, h_disc = 0;  // debug records only
+
+  // wave-uniform state
+  int wp = -1;
+  unsigned long long cur_next = 0, cur_end = 0, pend_next = 0, pend_end = 0;
+  int pend_p = -1;
+  bool qdone = false;
+  const PhantomDesc *D = P.desc;
+  unsigned long long hid0 = 0;
+
+  auto flush_wave = [&]() {
+    if (wp < 0) return;
+    const PhantomDesc *d = D;
+    if (lane >= 1 && lane < 6) {
+      const double x = wa.ledger[lane];
+      if (x != 0.0) atomicAdd(&d->ledger[lane], x);
+      wa.ledger[lane] = 0.0;
+    }
+    if (lane < kStatN) {
+      const unsigned long long x = wa.stat[lane];
+      if (lane == 9)
+        atomicMax(&d->stats[9], x);
+      else if (x)
+        atomicAdd(&d->stats[lane], x);
+      wa.stat[lane] = 0ull;
+    }
+    const int n_slots = d->n_org + 1;
+    for (int i = lane; i < n_slots; i += 64) {
+      const double2 o = s_org[wave][i];
+      if (o.x != 0.0 || o.y != 0.0) {
+        atomicAdd(&d->organ[i].x, o.x);
+        atomicAdd(&d->organ[i].y, o.y);
+      }
+      s_org[wave][i] = make_double2(0.0, 0.0);
+    }
+  };
+
+  auto start_photon = [&]() {
+    px = ox;
+    py = oy;
+    pz = oz;
+    const float sgn = photon == 0 ? 1.0f : -1.0f;
+    ux = sgn * dx0;
+    uy = sgn * dy0;
+    uz = sgn * dz0;
+    E = kE0;
+    n_real = 0;
+    psteps = 0;
+    ep = energy_params(E, P.ln2_kn, D->ln2_major, P.l2emin, P.inv_dl2);
+  };
+
+  auto start_history = [&](unsigned long long rel) {
+    run_rel = rel;
+    st.init(P.seed_lo, P.seed_hi, hid0 + rel, D->pid);
+    if (P.source_kind == 1) {
+      ox = P.po[0];
+      oy = P.po[1];
+      oz = P.po[2];
+      dx0 = P.pd[0];
+      dy0 = P.pd[1];
+      dz0 = P.pd[2];
+    } else {
+      // alias-table decay voxel: raw word for the column, uniform for the
+      // accept test, then a uniform position inside the voxel
+      const uint32_t x = st.word();
+      const uint32_t j = __umulhi(x, D->n_alias);
+      const float ua = st.uniform();
+      const uint4 a = D->alias[j];
+      const uint32_t v = ua < __uint_as_float(a.x) ? a.y : a.z;
+      const uint32_t nx = (uint32_t)D->nx;
+      const uint32_t nxy = nx * (uint32_t)D->ny;
+      const uint32_t iz = v / nxy;
+      const uint32_t r = v - iz * nxy;
+      const uint32_t iy = r / nx;
+      const uint32_t ix = r - iy * nx;
+      ox = ((float)ix + st.uniform()) * D->dx;
+      oy = ((float)iy + st.uniform()) * D->dy;
+      oz = ((float)iz + st.uniform()) * D->dz;
+      marsaglia(st, dx0, dy0, dz0);
+    }
+    photon = 0;
+    cnt = 0;
+    h_steps = h_nulls = h_cr = h_pe_esc = 0;
+    if (kDebug) h_esc = h_disc = 0.0;
+    start_photon();
+  };
+
+  // Score the history's merged deposit list: voxel sums S, S2 and the
+  // per-history organ scores.
+  auto flush_list = [&](bool final_flush) {
+    const PhantomDesc *d = D;
+    double edep = 0.0, sumv = 0.0;
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint32_t idx = j * L + gl;
+      const uint32_t v = P.dep_v[idx];
+      const double e = P.dep_e[idx];
+      atomicAdd(&d->tally[v].x, e);
+      atomicAdd(&d->tally[v].y, e * e);
+      if (kDebug) {
+        edep += e;
+        sumv += (double)v;
+      }
+    }
+    if (d->label) {
+      // q_o = sum over the history's voxels of organ o of e_v c / (m_v N_o)
+      for (uint32_t j = 0; j < cnt; ++j) {
+        const uint32_t idx = j * L + gl;
+        const uint32_t v = P.dep_v[idx];
+        const uint32_t o = d->label[v];
+        const float rho = s_pal[d->rec[v]].w;
+        P.dep_v[idx] = o;
+        P.dep_e[idx] = P.dep_e[idx] * d->organ_w[o] / (double)rho;
+      }
+      for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t ii = i * L + gl;
+        const uint32_t o = P.dep_v[ii];
+        if (o == 0 || o == 0xFFFFFFFFu) continue;
+        double q = P.dep_e[ii];
+        for (uint32_t j = i + 1; j < cnt; ++j) {
+          const uint32_t jj = j * L + gl;
+          if (P.dep_v[jj] == o) {
+            q += P.dep_e[jj];
+            P.dep_v[jj] = 0xFFFFFFFFu;
+          }
+        }
+        atomicAdd(&s_org[wave][o].x, q);
+        atomicAdd(&s_org[wave][o].y, q * q);
+      }
+    }
+    atomicAdd(&wa.stat[8], (unsigned long long)cnt);
+    atomicMax(&wa.stat[9], (unsigned long long)cnt);
+    if (kDebug && final_flush) {
+      double *r = P.hist_rec + run_rel * kRecN;
+      r[0] = edep;
+      r[1] = h_esc;
+      r[2] = h_cr & 0xFFFFu;
+      r[3] = h_pe_esc & 0xFFFFu;
+      r[4] = h_cr >> 16;
+      r[5] = h_steps;
+      r[6] = sumv;
+      r[7] = cnt;
+      r[8] = st.n_drawn;
+      r[9] = h_disc;
+    }
+    cnt = 0;
+  };
+
+  // Add energy e to voxel v in the history's deposit list (merged by voxel).
+  auto deposit = [&](uint32_t v, double e, int cause) {
+    atomicAdd(&wa.ledger[cause], e);
+    atomicAdd(&wa.stat[7], 1ull);
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint32_t idx = j * L + gl;
+      if (P.dep_v[idx] == v) {
+        P.dep_e[idx] += e;
+        return;
+      }
+    }
+    if (cnt == (uint32_t)kDepCap) {
+      atomicAdd(&wa.stat[11], 1ull);
+      flush_list(false);
+    }
+    const uint32_t idx = cnt * L + gl;
+    P.dep_v[idx] = v;
+    P.dep_e[idx] = e;
+    ++cnt;
+  };
+
+  for (;;) {
+    // ---- refill idle lanes from the wave's chunk, claiming chunks as needed
+    for (;;) {
+      const unsigned long long need = __ballot(!alive);
+      if (need == 0) break;
+      const bool any_alive = need != __ballot(1);
+      if (pend_p >= 0 && !any_alive) {
+        // switch phantom once every lane of the wave has finished
+        flush_wave();
+        wp = pend_p;
+        D = P.desc + P.slot[wp].id;
+        hid0 = P.slot[wp].hid0;
+        cur_next = pend_next;
+        cur_end = pend_end;
+        pend_p = -1;
+      }
+      if (cur_next < cur_end) {
+        const unsigned long long avail = cur_end - cur_next;
+        const uint32_t nneed = __popcll(need);
+        const uint32_t r = rank_in(need);
+        if (!alive && r < avail) {
+          start_history(cur_next + r);
+          alive = true;
+        }
+        cur_next += nneed < avail ? nneed : avail;
+        continue;
+      }
+      if (pend_p >= 0 || qdone) break;
+      unsigned long long c = 0;
+      if (lane == (uint32_t)(__ffsll((long long)__ballot(1)) - 1)) {
+        c = atomicAdd(&P.queue[0], 1ull);
+        if (P.abort_after && c >= P.abort_after) {
+          atomicExch(&P.queue[1], 1ull);
+          c = P.total_chunks;
+        }
+      }
+      c = uniform_u64(c);
+      if (c >= P.total_chunks) {
+        qdone = true;
+        break;
+      }
+      int p = 0;
+      while (p + 1 < P.n_ph && c >= P.slot[p + 1].chunk0) ++p;
+      p = __builtin_amdgcn_readfirstlane(p);
+      const unsigned long long first = (c - P.slot[p].chunk0) * (unsigned long long)P.chunk;
+      unsigned long long last = first + P.chunk;
+      last = last < P.slot[p].n_hist ? last : P.slot[p].n_hist;
+      if (lane == 0) atomicAdd(&P.desc[P.slot[p].id].stats[12], 1ull);
+      if (p == wp) {
+        cur_next = first;
+        cur_end = last;
+      } else {
+        pend_p = p;
+        pend_next = first;
+        pend_end = last;
+      }
+    }
+    if (__ballot(alive) == 0) {
+      if (pend_p >= 0) continue;
+      break;
+    }
+    if (!alive) continue;
+
+    // ---- one Woodcock step of this lane's photon
+    ++h_steps;
+    bool pdone = false;
+    {
+      const float s = -fast_log2(st.uniform()) * ep.inv_mu_ln2;
+      px += s * ux;
+      py += s * uy;
+      pz += s * uz;
+      const float fx = px * D->inv_dx, fy = py * D->inv_dy, fz = pz * D->inv_dz;
+      // written so that a NaN coordinate counts as outside
+      if (!(fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
+            fz < D->fnz)) {
+        atomicAdd(&wa.ledger[4], (double)E);
+        h_pe_esc += 0x10000u;
+        if (kDebug) h_esc += E;
+        pdone = true;
+      } else if (++psteps > kMaxPhotonSteps) {
+        // unreachable for valid input; bounds the loop for any input
+        atomicAdd(&wa.ledger[5], (double)E);
+        if (kDebug) h_disc += E;
+        pdone = true;
+      } else {
+        const uint32_t v =
+            (uint32_t)fx + (uint32_t)D->nx * ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz);
+        const float4 pal = s_pal[D->rec[v]];
+        const float mc = pal.x * ep.sig;
+        const float mpe = pal.y * ep.gpe;
+        const float mr = pal.z * ep.gr;
+        const float t = st.uniform() * ep.mu_hat;
+        int ev = t < mc ? 1 : (t < mc + mpe ? 2 : (t < mc + mpe + mr ? 3 : 0));
+        if (ev && !((P.mask >> (ev - 1)) & 1u)) ev = 0;
+        if (ev == 0) {
+          ++h_nulls;
+        } else {
+          ++n_real;
+          if (ev == 1) {
+            ++h_cr;
+            float cost;
+            const float eps = klein_nishina(st, E * (float)(1.0 / kMeC2), cost);
+            const float uphi = st.uniform();
+            const float e1 = eps * E;
+            deposit(v, (double)E - (double)e1, 1);
+            rotate(ux, uy, uz, cost, uphi);
+            E = e1;
+            if (E < P.cutoff) {
+              deposit(v, (double)E, 3);
+              pdone = true;
+            } else {
+              ep = energy_params(E, P.ln2_kn, D->ln2_major, P.l2emin, P.inv_dl2);
+            }
+          } else if (ev == 2) {
+            ++h_pe_esc;
+            deposit(v, (double)E, 2);
+            pdone = true;
+          } else {
+            h_cr += 0x10000u;
+            const float cost = thomson(st.uniform());
+            const float uphi = st.uniform();
+            rotate(ux, uy, uz, cost, uphi);
+          }
+          if (!pdone && P.max_real && n_real >= P.max_real) {
+            atomicAdd(&wa.ledger[5], (double)E);
+            if (kDebug) h_disc += E;
+            pdone = true;
+          }
+        }
+      }
+    }
+    if (pdone) {
+      if (photon + 1 < P.nph) {
+        ++photon;
+        start_photon();
+      } else {
+        atomicAdd(&wa.stat[0], 1ull);
+        atomicAdd(&wa.stat[1], (unsigned long long)P.nph);
+        atomicAdd(&wa.stat[2], (unsigned long long)h_steps);
+        atomicAdd(&wa.stat[3], (unsigned long long)h_nulls);
+        atomicAdd(&wa.stat[4], (unsigned long long)(h_cr & 0xFFFFu));
+        atomicAdd(&wa.stat[5], (unsigned long long)(h_pe_esc & 0xFFFFu));
+        atomicAdd(&wa.stat[6], (unsigned long long)(h_cr >> 16));
+        atomicAdd(&wa.stat[10], (unsigned long long)(h_pe_esc >> 16));
+        atomicAdd(&wa.stat[13], (unsigned long long)st.blk);
+        flush_list(true);
+        alive = false;
+      }
+    }
+  }
+  flush_wave();
+}
+
+int transport_occupancy_blocks_per_cu(bool debug) {
+  int nb = 0;
+  hipError_t e = debug ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true>, kBlock, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false>, kBlock, 0);
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_t s) {
+  if (debug)
+    hipLaunchKernelGGL(transport_kernel<true>, dim3(grid), dim3(kBlock), 0, s, p);
+  else
+    hipLaunchKernelGGL(transport_kernel<false>, dim3(grid), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: Eq. 1 per voxel
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void finalize_kernel(const uint8_t *__restrict__ rec,
+                                                       const float4 *__restrict__ palette,
+                                                       const double2 *__restrict__ tally,
+                                                       uint64_t nvox, double n, double vkg,
+                                                       double a_ts, double *__restrict__ rate,
+                                                       double *__restrict__ rel) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += stride) {
+    const double2 t = tally[v];
+    const double rho = (double)palette[rec[v]].w;
+    const double cm = kJPerMeV / (rho * vkg);
+    const double mean = t.x / n;
+    rate[v] = mean * cm * a_ts;
+    if (rel) {
+      double r = 0.0;
+      if (t.x > 0.0 && n > 1.0) {
+        double var = (t.y / n - mean * mean) / (n - 1.0);
+        var = var > 0.0 ? var : 0.0;
+        r = sqrt(var) / mean;
+      }
+      rel[v] = r;
+    }
+  }
+}
+
+hipError_t launch_finalize(const uint8_t *rec, const float4 *palette, const double2 *tally,
+                           uint64_t nvox, double n_decays, double vkg, double a_ts, double *rate,
+                           double *rel, hipStream_t s) {
+  uint64_t blocks = (nvox + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(finalize_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, rec, palette,
+                     tally, nvox, n_decays, vkg, a_ts, rate, rel);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Segmented organ reduction (Eq. 2, Eq. 3), fused with the per-voxel dose
+// rate and relative uncertainty of Eq. 1 so the maps need not exist.  Lanes
+// of a wave that share a label (neighbouring voxels mostly do) are summed
+// with shuffles, then one LDS atomic per (wave, label) and one global atomic
+// per (block, label).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void voxel_rate(const double2 t, double rho, double n, double vkg,
+                                           double a_ts, double &rate, double &rel) {
+  const double cm = kJPerMeV / (rho * vkg);
+  const double mean = t.x / n;
+  rate = mean * cm * a_ts;
+  rel = 0.0;
+  if (t.x > 0.0 && n > 1.0) {
+    double var = (t.y / n - mean * mean) / (n - 1.0);
+    var = var > 0.0 ? var : 0.0;
+    rel = sqrt(var) / mean;
+  }
+}
+
+__global__ __launch_bounds__(256) void organ_kernel(const uint8_t *__restrict__ rec,
+                                                    const uint8_t *__restrict__ label,
+                                                    const float4 *__restrict__ palette,
+                                                    const double2 *__restrict__ tally,
+                                                    uint64_t nvox, int n_org, double n,
+                                                    double vkg, double a_ts,
+                                                    double *__restrict__ out) {
+  __shared__ double2 s_acc[kMaxOrganSlots];
+  for (int i = threadIdx.x; i < kMaxOrganSlots; i += 256) s_acc[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t nround = (nvox + stride - 1) / stride;
+  uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = lane_id();
+  for (uint64_t it = 0; it < nround; ++it, v += stride) {
+    uint32_t o = 0;
+    double a = 0.0, b = 0.0;
+    if (v < nvox) {
+      o = label[v];
+      if (o != 0 && (int)o <= n_org) {
+        double r, e;
+        voxel_rate(tally[v], (double)palette[rec[v]].w, n, vkg, a_ts, r, e);
+        a = r;
+        b = e * e;
+      }
+    }
+    bool pending = o != 0 && (int)o <= n_org;
+    for (;;) {
+      const unsigned long long m = __ballot(pending);
+      if (m == 0) break;
+      const int lead = __ffsll((long long)m) - 1;
+      const uint32_t lo = __shfl(o, lead, 64);
+      const bool mine = pending && o == lo;
+      const double sa = wave_sum(mine ? a : 0.0);
+      const double sb = wave_sum(mine ? b : 0.0);
+      if ((int)lane == lead) {
+        atomicAdd(&s_acc[lo].x, sa);
+        atomicAdd(&s_acc[lo].y, sb);
+      }
+      pending = pending && !mine;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= n_org; i += 256) {
+    const double2 t = s_acc[i];
+    if (t.x != 0.0 || t.y != 0.0) {
+      atomicAdd(&out[2 * i], t.x);
+      atomicAdd(&out[2 * i + 1], t.y);
+    }
+  }
+}
+
+hipError_t launch_organ_reduce(const uint8_t *rec, const uint8_t *label, const float4 *palette,
+                               const double2 *tally, uint64_t nvox, int n_org, double n_decays,
+                               double vkg, double a_ts, double *acc, hipStream_t s) {
+  uint64_t blocks = (nvox + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(organ_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, rec, label, palette,
+                     tally, nvox, n_org, n_decays, vkg, a_ts, acc);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Test hooks
+// ---------------------------------------------------------------------------
+__global__ void debug_sample_kernel(int kind, float e_mev, uint64_t n, uint32_t s0, uint32_t s1,
+                                    double *out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Stream<false> st;
+  st.init(s0, s1, i, 0);
+  switch (kind) {
+    case 0:
+      for (int j = 0; j < 4; ++j) out[4 * i + j] = (double)st.word();
+      break;
+    case 1:
+      out[i] = (double)st.uniform();
+      break;
+    case 2: {
+      float x, y, z;
+      marsaglia(st, x, y, z);
+      out[3 * i] = x;
+      out[3 * i + 1] = y;
+      out[3 * i + 2] = z;
+      break;
+    }
+    case 3: {
+      float c;
+      const float eps = klein_nishina(st, e_mev * (float)(1.0 / kMeC2), c);
+      out[2 * i] = eps;
+      out[2 * i + 1] = c;
+      break;
+    }
+    case 5:
+      out[i] = (double)thomson(st.uniform());
+      break;
+    default:
+      break;
+  }
+}
+
+hipError_t launch_debug_sample(int kind, float e_mev, uint64_t n, uint32_t s0, uint32_t s1,
+                               double *out, hipStream_t s) {
+  const uint64_t blocks = (n + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(debug_sample_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, kind, e_mev, n,
+                     s0, s1, out);
+  return hipGetLastError();
+}
+
+__global__ void debug_source_kernel(const uint4 *alias, uint32_t n_alias, uint32_t pid, uint64_t n,
+                                    uint32_t s0, uint32_t s1, uint32_t *out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Stream<false> st;
+  st.init(s0, s1, i, pid);
+  const uint32_t x = st.word();
+  const uint32_t j = __umulhi(x, n_alias);
+  const float ua = st.uniform();
+  const uint4 a = alias[j];
+  out[i] = ua < __uint_as_float(a.x) ? a.y : a.z;
+}
+
+hipError_t launch_debug_source(const uint4 *alias, uint32_t n_alias, uint32_t pid, uint64_t n,
+                               uint32_t s0, uint32_t s1, uint32_t *out, hipStream_t s) {
+  const uint64_t blocks = (n + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(debug_source_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, alias, n_alias,
+                     pid, n, s0, s1, out);
+  return hipGetLastError();
+}
+
+__global__ void debug_xs_kernel(const float4 *palette, const uint8_t *used, int n_pal,
+                                const float *ln2_kn, const float *ln2_maj, uint64_t n,
+                                const float *energies, float *out, float l2emin, float inv_dl2) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const EnergyParams ep = energy_params(energies[i], ln2_kn, ln2_maj, l2emin, inv_dl2);
+  float mx = 0.0f;
+  for (int q = 0; q < n_pal; ++q) {
+    if (!used[q]) continue;
+    const float4 p = palette[q];
+    const float mc = p.x * ep.sig, mpe = p.y * ep.gpe, mr = p.z * ep.gr;
+    const float mt = mc + mpe + mr;
+    mx = mt > mx ? mt : mx;
+  }
+  out[2 * i] = ep.mu_hat;
+  out[2 * i + 1] = mx;
+}
+
+hipError_t launch_debug_xs(const float4 *palette, const uint8_t *used, int n_pal,
+                           const float *ln2_kn, const float *ln2_major, uint64_t n,
+                           const float *energies, float *out, float l2emin, float inv_dl2,
+                           hipStream_t s) {
+  const uint64_t blocks = (n + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(debug_xs_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, palette, used,
+                     n_pal, ln2_kn, ln2_major, n, energies, out, l2emin, inv_dl2);
+  return hipGetLastError();
+}
+
+__global__ void zero_kernel(uint32_t *p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+hipError_t launch_zero_bytes(void *p, uint64_t nbytes, hipStream_t s) {
+  const uint64_t n = nbytes / 4;  // callers pass multiples of 4 bytes
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, (uint32_t *)p, n);
+  return hipGetLastError();
+}
+
+}  // namespace nmd

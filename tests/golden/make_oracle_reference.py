@@ -1,0 +1,69 @@
+"""Write oracle_reference.json: FP64 oracle (exact traversal) results at
+10^8 decays for the slab phantom and the 256x256x320 patient phantom, used by
+the GPU parity tests at that size.  Calls only the oracle and the seeded
+input generators.
+
+For each case it stores the organ dose rates (Eq. 2, from per-history organ
+scores) with their relative standard errors, and the dose rate and relative
+uncertainty of every voxel with density >= 0.01 g/cm^3 and relative
+uncertainty <= 5 % (a seeded subset of at most 12000 of them).
+
+    python tests/golden/make_oracle_reference.py   (about 5 min on 8 cores)
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from paper_2111_11687_amd import phantoms as P  # noqa: E402
+
+MAX_VOXELS = 12000
+CASES = {
+    "slab128": (lambda: P.slab_phantom(), 10 ** 8, 5001),
+    "patient": (lambda: P.patient_phantom(), 10 ** 8, 5003),
+}
+
+
+def run_case(name):
+    make, n, seed = CASES[name]
+    prob = make()
+    ph = oracle.Phantom(prob.density, prob.material, [m[0] for m in prob.materials],
+                        [m[1] for m in prob.materials], prob.voxel_cm, label=prob.label,
+                        n_organs=prob.n_organs, activity=prob.activity)
+    t0 = time.time()
+    tal = None
+    done = 0
+    while done < n:  # in slices, so progress shows
+        k = min(10 ** 7, n - done)
+        tal, _ = oracle.run(ph, k, seed, tal, first_hist=done,
+                            photons_per_decay=prob.photons_per_decay)
+        done += k
+        print(name, done, "%.0f s" % (time.time() - t0), flush=True)
+    a = prob.total_activity_bq
+    rate, eps = oracle.finalize(ph, tal, a)
+    org, sig = oracle.organ_mean_sigma(tal, a)
+    m = (prob.density >= 0.01) & (eps > 0) & (eps <= 0.05)
+    idx = np.flatnonzero(m.ravel())
+    if len(idx) > MAX_VOXELS:  # a seeded subset keeps the fixture small
+        idx = np.sort(np.random.default_rng(seed).choice(idx, MAX_VOXELS, replace=False))
+    return {"n_decays": n, "seed": seed, "a_ts_bq": a, "threads_seconds": time.time() - t0,
+            "organ_rate": org.tolist(), "organ_rel_sigma": sig.tolist(),
+            "ledger": tal.ledger, "stats": tal.stats,
+            "voxel_index": idx.tolist(),
+            "voxel_rate": [float("%.12g" % x) for x in rate.ravel()[idx]],
+            "voxel_rel": [float("%.12g" % x) for x in eps.ravel()[idx]]}
+
+
+if __name__ == "__main__":
+    out = {"generator": "tests/golden/make_oracle_reference.py",
+           "oracle": "oracle/nmd_oracle.c, exact traversal, Kahn KN sampler, 53-bit uniforms"}
+    for name in CASES:
+        out[name] = run_case(name)
+    with open(os.path.join(HERE, "oracle_reference.json"), "w") as f:
+        json.dump(out, f)

@@ -1,0 +1,90 @@
+"""Draw-for-draw replay: the device transport and the oracle's Woodcock mode
+consume the same Philox stream in the same order, so every history's event
+counts, step count and number of uniforms agree exactly, and its deposited
+and escaped energy agree to FP32 rounding.  FP32 positions may put a rare
+history on the other side of a voxel face; the bar allows 0.5 %."""
+import numpy as np
+import pytest
+
+from conftest import ledger_balance, oracle_phantom
+from paper_2111_11687_amd import phantoms as P
+
+pytestmark = pytest.mark.gpu
+INT_COLS = [2, 3, 4, 5, 8]  # n_compton, n_pe, n_rayleigh, n_steps, n_uniforms
+
+
+def _replay(engine, orc, pid, prob, n, seed, **kw):
+    engine.set_problem(pid, prob)
+    t = engine.torch
+    rec = t.zeros(n * 10, dtype=t.float64, device=engine.device)
+    gkw = dict(kw)
+    okw = {}
+    if "pencil" in kw:
+        o, d = gkw.pop("pencil")
+        gkw.update(source_kind=1, pencil_origin_cm=o, pencil_dir=d)
+        okw["pencil"] = (o, d)
+    for k in ("photons_per_decay", "process_mask", "max_real_events"):
+        if k in kw:
+            okw[k] = kw[k]
+    engine.run(pid, n, seed, history_records=rec, **gkw)
+    g = rec.cpu().numpy().reshape(n, 10)
+    ph = oracle_phantom(orc, prob)
+    _, o = orc.run(ph, n, seed, tracking=orc.TRACK_WOODCOCK, pid=pid, history_records=True,
+                   **okw)
+    return g, o
+
+
+def _check(g, o, frac=0.995):
+    same = np.all(g[:, INT_COLS] == o[:, INT_COLS], axis=1)
+    assert same.mean() >= frac, "identical event counts: %.5f" % same.mean()
+    e_ok = np.abs(g[:, 0] - o[:, 0]) <= 1e-5 + 1e-5 * np.abs(o[:, 0])
+    x_ok = np.abs(g[:, 1] - o[:, 1]) <= 1e-5 + 1e-5 * np.abs(o[:, 1])
+    assert (same & e_ok & x_ok).mean() >= frac
+    # where the histories agree, the deposit voxels agree too
+    v_ok = g[same, 7] == o[same, 7]
+    assert v_ok.mean() >= frac
+
+
+def test_replay_water_point_source(engine, orc):
+    prob = P.water_point_source(n=32, voxel_mm=2.0)
+    g, o = _replay(engine, orc, 10, prob, 30_000, 5, photons_per_decay=1)
+    _check(g, o)
+
+
+def test_replay_slab_pairs(engine, orc):
+    prob = P.slab_phantom(n=64, voxel_mm=6.0)
+    g, o = _replay(engine, orc, 11, prob, 30_000, 7)
+    _check(g, o)
+    assert (g[:, 2] > 0).mean() > 0.2
+
+
+def test_replay_pencil_through_lung_and_bone(engine, orc):
+    prob = P.slab_phantom()
+    h = prob.voxel_cm[0]
+    iz = int(prob.extra["cyl_xz"][1])
+    origin = (0.0, 64.5 * h, (iz + 0.5) * h)
+    g, o = _replay(engine, orc, 12, prob, 30_000, 9, pencil=(origin, (1.0, 0.0, 0.0)))
+    _check(g, o)
+
+
+def test_replay_masks_and_first_collision(engine, orc):
+    prob = P.slab_phantom(n=64, voxel_mm=6.0)
+    g, o = _replay(engine, orc, 13, prob, 20_000, 11, process_mask=1, max_real_events=1)
+    _check(g, o)
+    assert g[:, 3].sum() == 0 and g[:, 4].sum() == 0
+    assert np.all(g[:, 2] <= 2)
+    g, o = _replay(engine, orc, 13, prob, 20_000, 12, process_mask=2 | 4)
+    _check(g, o)
+    assert g[:, 2].sum() == 0
+
+
+def test_replay_full_size_patient_pencil(engine, orc):
+    """At the benchmark's full 256x256x320 size and launch shape: pencil
+    histories through the head and torso, replayed one by one."""
+    prob = P.patient_phantom()
+    h = prob.voxel_cm
+    origin = (0.0, 128.5 * h[1], 250.5 * h[2])
+    g, o = _replay(engine, orc, 14, prob, 20_000, 13, pencil=(origin, (1.0, 0.0, 0.0)))
+    _check(g, o)
+    led = engine.ledger(14)
+    assert abs(ledger_balance(led)) < 1e-9
