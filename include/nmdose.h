@@ -113,7 +113,8 @@ void nmd_run_opts_default(nmd_run_opts *opts);
  * (Section 2.3).  density: device float[nvox], finite and > 0;
  * material: device uint8[nvox], < n_materials; organ_label: device
  * uint8[nvox] or NULL, 0 = no organ, 1..n_organs; materials: host
- * [n_materials], n_materials <= 8.  nvox = nx*ny*nz must be < 2^31.
+ * [n_materials], n_materials <= 8.  nx, ny <= 1024 and nz <= 4096
+ * (NMD_E_UNSUPPORTED beyond).
  * Re-registering an id drops its activity and tallies.  Distinct
  * (material, density) pairs over all phantoms of a context are limited to
  * 256 (NMD_E_UNSUPPORTED beyond).  Synchronises the stream. */

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -59,11 +60,12 @@ struct Phantom {
   int32_t nx = 0, ny = 0, nz = 0, n_org = 0;
   double dx = 0, dy = 0, dz = 0;  // cm
   uint64_t nvox = 0;
-  DevBuf rec, label, alias, tally, organ, ledger, stats, major, organ_w;
+  DevBuf rec, alias, tally, organ, ledger, stats, major, organ_w;  // rec: u16 per voxel
   std::vector<int64_t> organ_count;  // voxels per label 0..n_org
   std::vector<uint8_t> used;         // palette entries present
   uint32_t n_alias = 0;
   bool has_activity = false;
+  bool has_label = false;
   double a_ts = 0.0;
   uint64_t n_done = 0;
   double vkg() const { return dx * dy * dz * 1.0e-3; }  // kg per (g/cm^3)
@@ -82,10 +84,11 @@ struct nmd_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   std::vector<PalEntry> pal;
-  DevBuf d_pal, d_kn, d_queue, d_desc, d_dep_v, d_dep_e, d_acc;
+  DevBuf d_pal, d_kn, d_queue, d_desc, d_dep_v, d_dep_e, d_dep_r, d_acc;
   uint32_t dep_lanes = 0;
   int cu_count = 0;
   float l2emin = 0, inv_dl2 = 0;
+  uint32_t phase_min = 32;  // tuning: NMD_PHASE_MIN
   std::map<int, Phantom> ph;
   bool poisoned = false;
 };
@@ -155,6 +158,13 @@ float round_up_f32(double x) {
   return f;
 }
 
+// Voxel coordinates packed as x | y << 10 | z << 20 (grid limits 1024 x 1024 x 4096).
+uint32_t pack_xyz(const Phantom &p, uint32_t v) {
+  const uint32_t nx = (uint32_t)p.nx, nxy = nx * (uint32_t)p.ny;
+  const uint32_t z = v / nxy, r = v - z * nxy, y = r / nx, x = r - y * nx;
+  return x | (y << 10) | (z << 20);
+}
+
 nmd_status sync(nmd_ctx *c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return NMD_OK;
@@ -174,8 +184,7 @@ Phantom *find(nmd_ctx *c, int32_t id) {
 
 nmd_status upload_desc(nmd_ctx *c, int32_t id, Phantom &p) {
   PhantomDesc d = {};
-  d.rec = p.rec.as<uint8_t>();
-  d.label = p.label.as<uint8_t>();
+  d.rec = p.rec.as<uint16_t>();
   d.alias = p.alias.as<uint4>();
   d.tally = p.tally.as<double2>();
   d.organ = p.organ.as<double2>();
@@ -258,6 +267,10 @@ nmd_status nmd_create(nmd_ctx **out, int device, void *stream) {
     return NMD_E_HIP;
   }
   c->cu_count = prop.multiProcessorCount;
+  if (const char *e = std::getenv("NMD_PHASE_MIN")) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 1 && v <= 64) c->phase_min = (uint32_t)v;
+  }
   c->l2emin = (float)std::log2(kEGridMin);
   c->inv_dl2 = (float)((kNGrid - 1) / std::log2(kEGridRatio));
   std::vector<float> kn(kNGrid);
@@ -311,6 +324,8 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
     return fail(c, NMD_E_SHAPE, "dimensions must be >= 1 (%d, %d, %d)", nx, ny, nz);
   const uint64_t nvox = (uint64_t)nx * ny * nz;
   if (nvox >= (1ull << 31)) return fail(c, NMD_E_SHAPE, "nx*ny*nz must be < 2^31");
+  if (nx > 1024 || ny > 1024 || nz > 4096)
+    return fail(c, NMD_E_UNSUPPORTED, "grids are limited to 1024 x 1024 x 4096 voxels");
   if (!(dx_mm > 0 && dy_mm > 0 && dz_mm > 0) || !std::isfinite(dx_mm) || !std::isfinite(dy_mm) ||
       !std::isfinite(dz_mm))
     return fail(c, NMD_E_INVALID, "voxel sizes must be finite and > 0");
@@ -331,7 +346,7 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
   std::vector<PalEntry> pal = c->pal;
   std::unordered_map<uint64_t, int> key_to_q;
   std::vector<int> mat_pal_base(n_mat);
-  std::vector<uint8_t> rec(nvox);
+  std::vector<uint16_t> rec(nvox);
   std::vector<uint8_t> used(kMaxPalette, 0);
   uint64_t last_key = ~0ull;
   int last_q = 0;
@@ -375,7 +390,7 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
       last_key = key;
       last_q = it->second;
     }
-    rec[v] = (uint8_t)last_q;
+    rec[v] = (uint16_t)(last_q | (label ? (uint32_t)h_lab[v] << 8 : 0u));
     used[last_q] = 1;
   }
   std::vector<int64_t> count(n_organs + 1, 0);
@@ -419,17 +434,16 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
   for (int o = 0; o <= n_organs; ++o)
     ow[o] = count[o] > 0 ? kJPerMeV / (p.vkg() * (double)count[o]) : 0.0;
 
-  if ((s = dev_alloc(c, p.rec, nvox)) || (s = dev_alloc(c, p.tally, nvox * sizeof(double2))) ||
+  p.has_label = label != nullptr;
+  if ((s = dev_alloc(c, p.rec, nvox * sizeof(uint16_t))) || (s = dev_alloc(c, p.tally, nvox * sizeof(double2))) ||
       (s = dev_alloc(c, p.organ, (n_organs + 1) * sizeof(double2))) ||
       (s = dev_alloc(c, p.ledger, 8 * sizeof(double))) ||
       (s = dev_alloc(c, p.stats, 16 * sizeof(unsigned long long))) ||
       (s = dev_alloc(c, p.major, kNGrid * sizeof(float))) ||
       (s = dev_alloc(c, p.organ_w, (n_organs + 1) * sizeof(double))))
     return s;
-  if (label && (s = dev_alloc(c, p.label, nvox))) return s;
-  HIP_TRY(c, hipMemcpyAsync(p.rec.p, rec.data(), nvox, hipMemcpyHostToDevice, c->stream));
-  if (label)
-    HIP_TRY(c, hipMemcpyAsync(p.label.p, h_lab.data(), nvox, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p.rec.p, rec.data(), nvox * sizeof(uint16_t), hipMemcpyHostToDevice,
+                            c->stream));
   HIP_TRY(c, hipMemcpyAsync(p.major.p, maj.data(), kNGrid * sizeof(float), hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, hipMemcpyAsync(p.organ_w.p, ow.data(), ow.size() * sizeof(double),
@@ -495,7 +509,7 @@ nmd_status nmd_set_activity(nmd_ctx *c, int32_t id, const float *act, double tot
     float pr = (float)prob[i];
     uint32_t pb;
     std::memcpy(&pb, &pr, 4);
-    tab[i] = make_uint4(pb, nz[i], nz[alias[i]], 0u);
+    tab[i] = make_uint4(pb, pack_xyz(*p, nz[i]), pack_xyz(*p, nz[alias[i]]), 0u);
   }
   DevBuf d;
   if ((s = dev_alloc(c, d, n * sizeof(uint4)))) return s;
@@ -571,13 +585,16 @@ nmd_status nmd_run_histories(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
   }
 
   // launch shape
-  const int per_cu = transport_occupancy_blocks_per_cu(o.history_records != nullptr);
+  int n_slots = 1;
+  for (int32_t i : ids) n_slots = std::max(n_slots, c->ph[i].n_org + 1);
+  const int per_cu = transport_occupancy_blocks_per_cu(o.history_records != nullptr, n_slots);
   uint32_t grid = o.grid_blocks ? o.grid_blocks : (uint32_t)(c->cu_count * per_cu);
-  grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, 65536));
+  grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, 8192));
   const uint32_t lanes = grid * kBlock;
   if (lanes > c->dep_lanes) {
     if ((s = dev_alloc(c, c->d_dep_v, (size_t)lanes * kDepCap * sizeof(uint32_t))) ||
-        (s = dev_alloc(c, c->d_dep_e, (size_t)lanes * kDepCap * sizeof(double)))) {
+        (s = dev_alloc(c, c->d_dep_e, (size_t)lanes * kDepCap * sizeof(double))) ||
+        (s = dev_alloc(c, c->d_dep_r, (size_t)lanes * kDepCap * sizeof(uint32_t)))) {
       c->dep_lanes = 0;
       return s;
     }
@@ -626,6 +643,9 @@ nmd_status nmd_run_histories(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
   rp.inv_dl2 = c->inv_dl2;
   rp.dep_v = c->d_dep_v.as<uint32_t>();
   rp.dep_e = c->d_dep_e.as<double>();
+  rp.dep_r = c->d_dep_r.as<uint32_t>();
+  rp.n_slots = n_slots;
+  rp.phase_min = c->phase_min;
   rp.n_lanes = lanes;
   rp.hist_rec = o.history_records;
 
@@ -649,7 +669,7 @@ nmd_status nmd_get_dose(nmd_ctx *c, int32_t id, double *rate, double *rel) {
   if (!p->has_activity || p->n_done == 0)
     return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
   if (!rate) return fail(c, NMD_E_INVALID, "dose_rate buffer is required");
-  HIP_TRY(c, launch_finalize(p->rec.as<uint8_t>(), c->d_pal.as<float4>(), p->tally.as<double2>(),
+  HIP_TRY(c, launch_finalize(p->rec.as<uint16_t>(), c->d_pal.as<float4>(), p->tally.as<double2>(),
                              p->nvox, (double)p->n_done, p->vkg(), p->a_ts, rate, rel, c->stream));
   return NMD_OK;
 }
@@ -660,7 +680,7 @@ nmd_status nmd_get_organ_dose(nmd_ctx *c, int32_t id, int32_t n_organs, double *
   if (s) return s;
   Phantom *p = find(c, id);
   if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
-  if (!p->label.p) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
+  if (!p->has_label) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
   if (!p->has_activity || p->n_done == 0)
     return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
   if (n_organs < 0 || n_organs > p->n_org)
@@ -668,8 +688,7 @@ nmd_status nmd_get_organ_dose(nmd_ctx *c, int32_t id, int32_t n_organs, double *
   const double n = (double)p->n_done;
   if (rate || eps3) {
     HIP_TRY(c, launch_zero_bytes(c->d_acc.p, (p->n_org + 1) * 2 * sizeof(double), c->stream));
-    HIP_TRY(c, launch_organ_reduce(p->rec.as<uint8_t>(), p->label.as<uint8_t>(),
-                                   c->d_pal.as<float4>(), p->tally.as<double2>(), p->nvox,
+    HIP_TRY(c, launch_organ_reduce(p->rec.as<uint16_t>(), c->d_pal.as<float4>(), p->tally.as<double2>(), p->nvox,
                                    p->n_org, n, p->vkg(), p->a_ts, c->d_acc.as<double>(),
                                    c->stream));
     std::vector<double> acc((p->n_org + 1) * 2);
@@ -702,7 +721,7 @@ nmd_status nmd_get_organ_score(nmd_ctx *c, int32_t id, int32_t n_organs, double 
   if (s) return s;
   Phantom *p = find(c, id);
   if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
-  if (!p->label.p) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
+  if (!p->has_label) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
   if (n_organs < 0 || n_organs > p->n_org || !rate)
     return fail(c, NMD_E_INVALID, "bad n_organs or output");
   if (p->n_done == 0) return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
@@ -799,7 +818,8 @@ nmd_status nmd_debug_sample_source(nmd_ctx *c, int32_t id, uint64_t n, uint64_t 
   if (!p || !p->has_activity) return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
   if (!out && n) return fail(c, NMD_E_INVALID, "output is required");
   HIP_TRY(c, launch_debug_source(p->alias.as<uint4>(), p->n_alias, (uint32_t)id, n, (uint32_t)seed,
-                                 (uint32_t)(seed >> 32), out, c->stream));
+                                 (uint32_t)(seed >> 32), (uint32_t)p->nx, (uint32_t)p->ny, out,
+                                 c->stream));
   return NMD_OK;
 }
 

@@ -12,24 +12,32 @@ __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_lo
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplies with a Weyl-sequence key schedule.
+// 32x32->64 multiplies (one v_mad_u64_u32 each) with a Weyl-sequence key
+// schedule.
+// kUnroll: straight-line rounds (used where all lanes refill together)
+// or a compact loop (the rarer refills inside the physics).
+template <bool kUnroll = false>
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t &o0,
                                               uint32_t &o1, uint32_t &o2, uint32_t &o3) {
-#pragma unroll 1
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+  auto round = [&]() {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
     c0 = n0;
-    c1 = lo1;
     c2 = n2;
-    c3 = lo0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
+  };
+  if constexpr (kUnroll) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) round();
+  } else {
+#pragma unroll 1
+    for (int r = 0; r < 10; ++r) round();
   }
   o0 = c0;
   o1 = c1;
@@ -38,12 +46,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 }
 
 // Random stream of one history: counter (block, hid_lo, hid_hi, phantom),
-// key (seed_lo, seed_hi); the four words of a block are handed out in order.
+// key (seed_lo, seed_hi); the words of each block are handed out in order.
+// Up to five words are buffered in b0..b4 and consumed from b0 with a shift,
+// so no word is ever selected by a run-time index (which would put the
+// buffer in scratch memory).
 template <bool kCount>
 struct Stream {
   uint32_t k0, k1, h0, h1, pid, blk;
-  uint32_t b0, b1, b2, b3;
-  uint32_t pos;
+  uint32_t b0, b1, b2, b3, b4;
+  uint32_t pos;      // words buffered
   uint32_t n_drawn;  // uniforms handed out (debug records only)
 
   __device__ __forceinline__ void init(uint32_t seed_lo, uint32_t seed_hi, unsigned long long hid,
@@ -54,24 +65,54 @@ struct Stream {
     h1 = (uint32_t)(hid >> 32);
     pid = p;
     blk = 0;
-    pos = 4;
+    pos = 0;
     n_drawn = 0;
   }
-  __device__ __forceinline__ uint32_t word() {
-    if (pos == 4) {
-      philox4x32_10(blk, h0, h1, pid, k0, k1, b0, b1, b2, b3);
+  // Make sure at least two words are buffered (one block is appended).
+  __device__ __forceinline__ void reserve2() {
+    if (pos < 2) {
+      uint32_t n0, n1, n2, n3;
+      philox4x32_10<true>(blk, h0, h1, pid, k0, k1, n0, n1, n2, n3);
       ++blk;
-      pos = 0;
+      if (pos == 0) {
+        b0 = n0;
+        b1 = n1;
+        b2 = n2;
+        b3 = n3;
+      } else {
+        b1 = n0;
+        b2 = n1;
+        b3 = n2;
+        b4 = n3;
+      }
+      pos += 4;
     }
-    const uint32_t x = pos == 0 ? b0 : (pos == 1 ? b1 : (pos == 2 ? b2 : b3));
-    ++pos;
+  }
+  // Next word; the caller guarantees one is buffered.
+  __device__ __forceinline__ uint32_t take() {
+    const uint32_t x = b0;
+    b0 = b1;
+    b1 = b2;
+    b2 = b3;
+    b3 = b4;
+    --pos;
     if (kCount) ++n_drawn;
     return x;
   }
-  // ((x >> 9) + 1/2) * 2^-23: exactly representable, strictly inside (0, 1).
-  __device__ __forceinline__ float uniform() {
-    return ((float)(word() >> 9) + 0.5f) * (1.0f / 8388608.0f);
+  __device__ __forceinline__ uint32_t word() {
+    if (pos == 0) {
+      philox4x32_10(blk, h0, h1, pid, k0, k1, b0, b1, b2, b3);
+      ++blk;
+      pos = 4;
+    }
+    return take();
   }
+  static __device__ __forceinline__ float to_uniform(uint32_t x) {
+    // ((x >> 9) + 1/2) * 2^-23: exactly representable, strictly inside (0, 1)
+    return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f);
+  }
+  __device__ __forceinline__ float uniform() { return to_uniform(word()); }
+  __device__ __forceinline__ float take_uniform() { return to_uniform(take()); }
 };
 
 // Isotropic direction, Marsaglia (1972).
@@ -156,8 +197,8 @@ struct EnergyParams {
   float sig, gpe, gr, mu_hat, inv_mu_ln2;
 };
 
-__device__ __forceinline__ EnergyParams energy_params(float E, const float *__restrict__ ln2_kn,
-                                                      const float *__restrict__ ln2_maj,
+__device__ __forceinline__ EnergyParams energy_params(float E, const float *ln2_kn,
+                                                      const float *ln2_maj,
                                                       float l2emin, float inv_dl2) {
   EnergyParams p;
   const float t = (fast_log2(E) - l2emin) * inv_dl2;

@@ -10,12 +10,19 @@ constexpr int kMaxPhantoms = 64;
 constexpr int kMaxPalette = 256;        // u8 voxel records
 constexpr int kNGrid = 256;             // energy nodes, 1 keV .. 511 keV
 constexpr int kDepCap = 64;             // distinct deposit voxels kept per history
+constexpr int kRegDep = 4;              // of which held in registers
 constexpr int kBlock = 256;             // transport workgroup size (4 waves)
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kMaxOrganSlots = 256;     // labels 0..255
 constexpr int kRecN = 10;               // per-history debug record width
 constexpr int kStatN = 14;
 constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
+
+// Workgroups of the transport kernel the compiler must fit on one CU (it
+// caps registers accordingly); a build-time tuning knob.
+#ifndef NMD_TRANSPORT_MIN_BLOCKS
+#define NMD_TRANSPORT_MIN_BLOCKS 3
+#endif
 
 // Model constants.
 constexpr double kMeC2 = 0.51099895;            // MeV
@@ -31,9 +38,8 @@ constexpr float kKappa = 1.0f + 1.0f / 16384.0f;  // majorant inflation
 
 // Static per-phantom descriptor (device array indexed by phantom id).
 struct PhantomDesc {
-  const uint8_t *rec;        // palette index per voxel
-  const uint8_t *label;      // organ label per voxel, or nullptr
-  const uint4 *alias;        // {prob bits, voxel, alias voxel, 0}
+  const uint16_t *rec;       // per voxel: palette index | organ label << 8
+  const uint4 *alias;        // {prob bits, voxel, alias voxel, 0}; voxels as x | y<<10 | z<<20
   double2 *tally;            // (S, S2) per voxel
   double2 *organ;            // (O, O2) per label slot
   double *ledger;            // [6]
@@ -74,27 +80,31 @@ struct RunParams {
   int32_t n_pal;
   const float *ln2_kn;       // [kNGrid] log2(N_A sigma_KN(E_i))
   float l2emin, inv_dl2;     // grid coordinate t = (log2 E - l2emin) * inv_dl2
-  uint32_t *dep_v;           // [kDepCap][n_lanes]
-  double *dep_e;             // [kDepCap][n_lanes]
+  uint32_t *dep_v;           // overflow deposit lists [kDepCap][n_lanes]: voxel
+  double *dep_e;             //   energy
+  uint32_t *dep_r;           //   voxel record
+  int32_t n_slots;           // largest n_org + 1 of the launch's phantoms
+  uint32_t phase_min;        // lanes that must wait before a phase runs
   uint32_t n_lanes;
   double *hist_rec;          // debug [n_hist][kRecN] or nullptr
   RunSlot slot[kMaxPhantoms];
 };
 
 hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_t s);
-int transport_occupancy_blocks_per_cu(bool debug);
-hipError_t launch_finalize(const uint8_t *rec, const float4 *palette, const double2 *tally,
+int transport_occupancy_blocks_per_cu(bool debug, int n_slots);
+size_t transport_dyn_lds_bytes(int n_slots);
+hipError_t launch_finalize(const uint16_t *rec, const float4 *palette, const double2 *tally,
                            uint64_t nvox, double n_decays, double voxel_kg_per_rho,
                            double a_ts, double *rate, double *rel, hipStream_t s);
-hipError_t launch_organ_reduce(const uint8_t *rec, const uint8_t *label, const float4 *palette,
+hipError_t launch_organ_reduce(const uint16_t *rec, const float4 *palette,
                                const double2 *tally, uint64_t nvox, int n_org, double n_decays,
                                double voxel_kg_per_rho, double a_ts,
                                double *acc /* [(n_org+1)*2] */, hipStream_t s);
 hipError_t launch_debug_sample(int kind, float e_mev, uint64_t n, uint32_t seed_lo,
                                uint32_t seed_hi, double *out, hipStream_t s);
 hipError_t launch_debug_source(const uint4 *alias, uint32_t n_alias, uint32_t pid, uint64_t n,
-                               uint32_t seed_lo, uint32_t seed_hi, uint32_t *out,
-                               hipStream_t s);
+                               uint32_t seed_lo, uint32_t seed_hi, uint32_t nx, uint32_t ny,
+                               uint32_t *out, hipStream_t s);
 hipError_t launch_debug_xs(const float4 *palette, const uint8_t *used, int n_pal,
                            const float *ln2_kn, const float *ln2_major, uint64_t n,
                            const float *energies, float *out, float l2emin, float inv_dl2,

@@ -58,34 +58,87 @@ struct WaveAcc {
   unsigned long long stat[kStatN];
 };
 
+// Per-wave part of the dynamic LDS: organ score accumulators, majorant table
+// of the wave's current phantom and its organ weights.  Each wave's region
+// is a whole number of 16-byte units, so the double2 accumulators stay
+// 16-byte aligned.
+struct WaveLds {
+  double2 *org;  // [n_slots]
+  float *maj;    // [kNGrid]
+  double *w;     // [n_slots]
+};
+
+__host__ __device__ inline size_t wave_lds_units(int n_slots) {  // 16-byte units
+  return (size_t)n_slots + (size_t)kNGrid / 4 + ((size_t)n_slots + 1) / 2;
+}
+
+__device__ __forceinline__ WaveLds wave_lds(double2 *dyn, uint32_t wave, int n_slots) {
+  double2 *base = dyn + wave_lds_units(n_slots) * wave;
+  WaveLds w;
+  w.org = base;
+  w.maj = reinterpret_cast<float *>(base + n_slots);
+  w.w = reinterpret_cast<double *>(base + n_slots + kNGrid / 4);
+  return w;
+}
+
+size_t transport_dyn_lds_bytes(int n_slots) {
+  return (size_t)kWavesPerBlock * wave_lds_units(n_slots) * sizeof(double2);
+}
+
+// Make this wave's LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <bool kDebug>
-__global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
+__global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_kernel(RunParams P) {
   __shared__ float4 s_pal[kMaxPalette];
-  __shared__ double2 s_org[kWavesPerBlock][kMaxOrganSlots];
+  __shared__ double s_irho[kMaxPalette];  // 1 / density, for the organ scores
+  __shared__ float s_kn[kNGrid];
   __shared__ WaveAcc s_acc[kWavesPerBlock];
+  __shared__ float s_start[kWavesPerBlock][6][64];  // decay point and first direction
+  extern __shared__ double2 s_dyn[];
 
   const uint32_t tid = threadIdx.x;
   const uint32_t wave = tid >> 6;
   const uint32_t lane = lane_id();
-  const uint32_t gl = blockIdx.x * kBlock + tid;  // lane slot in the deposit lists
+  const uint32_t gl = blockIdx.x * kBlock + tid;  // lane slot in the overflow lists
   const uint32_t L = P.n_lanes;
   WaveAcc &wa = s_acc[wave];
+  const WaveLds wl = wave_lds(s_dyn, wave, P.n_slots);
+  float(&sst)[6][64] = s_start[wave];
 
-  for (int i = tid; i < P.n_pal; i += kBlock) s_pal[i] = P.palette[i];
-  for (int i = lane; i < kMaxOrganSlots; i += 64) s_org[wave][i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < P.n_pal; i += kBlock) {
+    const float4 q = P.palette[i];
+    s_pal[i] = q;
+    s_irho[i] = 1.0 / (double)q.w;
+  }
+  for (int i = tid; i < kNGrid; i += kBlock) s_kn[i] = P.ln2_kn[i];
   if (lane < 6) wa.ledger[lane] = 0.0;
   if (lane < kStatN) wa.stat[lane] = 0ull;
   __syncthreads();
 
   Stream<kDebug> st;
 
-  // lane state
-  bool alive = false;
+  // lane state: which phase the lane waits for
+  constexpr uint32_t kIdle = 0, kFlight = 1, kInteract = 2, kPhotonEnd = 3;
+  uint32_t state = kIdle;
+  uint32_t ev_v = 0, ev_r = 0;  // pending interaction: voxel and its record
+  int ev_t = 0;                 // 1 Compton, 2 photoelectric, 3 Rayleigh
   float px = 0, py = 0, pz = 0, ux = 0, uy = 0, uz = 0, E = 0;
-  float ox = 0, oy = 0, oz = 0, dx0 = 0, dy0 = 0, dz0 = 0;
   uint32_t photon = 0, n_real = 0, cnt = 0, psteps = 0;
   uint32_t h_steps = 0, h_nulls = 0, h_cr = 0, h_pe_esc = 0;  // per-history counts
   EnergyParams ep = {};
+  // first kRegDep distinct deposit voxels of the history, in registers
+  uint32_t rv[kRegDep], rr[kRegDep];
+  double re[kRegDep];
+#pragma unroll
+  for (int i = 0; i < kRegDep; ++i) {
+    rv[i] = 0u;
+    rr[i] = 0u;
+    re[i] = 0.0;
+  }
   unsigned long long run_rel = 0;
   double h_esc = 0, h_disc = 0;  // debug records only
 
@@ -115,39 +168,49 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
     }
     const int n_slots = d->n_org + 1;
     for (int i = lane; i < n_slots; i += 64) {
-      const double2 o = s_org[wave][i];
+      const double2 o = wl.org[i];
       if (o.x != 0.0 || o.y != 0.0) {
         atomicAdd(&d->organ[i].x, o.x);
         atomicAdd(&d->organ[i].y, o.y);
       }
-      s_org[wave][i] = make_double2(0.0, 0.0);
     }
   };
 
+  // load the wave's per-phantom LDS tables
+  auto enter_phantom = [&]() {
+    for (int i = lane; i < kNGrid; i += 64) wl.maj[i] = D->ln2_major[i];
+    for (int i = lane; i <= D->n_org; i += 64) {
+      wl.w[i] = D->organ_w[i];
+      wl.org[i] = make_double2(0.0, 0.0);
+    }
+    wave_lds_sync();
+  };
+
   auto start_photon = [&]() {
-    px = ox;
-    py = oy;
-    pz = oz;
     const float sgn = photon == 0 ? 1.0f : -1.0f;
-    ux = sgn * dx0;
-    uy = sgn * dy0;
-    uz = sgn * dz0;
+    px = sst[0][lane];
+    py = sst[1][lane];
+    pz = sst[2][lane];
+    ux = sgn * sst[3][lane];
+    uy = sgn * sst[4][lane];
+    uz = sgn * sst[5][lane];
     E = kE0;
     n_real = 0;
     psteps = 0;
-    ep = energy_params(E, P.ln2_kn, D->ln2_major, P.l2emin, P.inv_dl2);
+    ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
   };
 
   auto start_history = [&](unsigned long long rel) {
     run_rel = rel;
     st.init(P.seed_lo, P.seed_hi, hid0 + rel, D->pid);
+    float o0, o1, o2, d0, d1, d2;
     if (P.source_kind == 1) {
-      ox = P.po[0];
-      oy = P.po[1];
-      oz = P.po[2];
-      dx0 = P.pd[0];
-      dy0 = P.pd[1];
-      dz0 = P.pd[2];
+      o0 = P.po[0];
+      o1 = P.po[1];
+      o2 = P.po[2];
+      d0 = P.pd[0];
+      d1 = P.pd[1];
+      d2 = P.pd[2];
     } else {
       // alias-table decay voxel: raw word for the column, uniform for the
       // accept test, then a uniform position inside the voxel
@@ -155,31 +218,44 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
       const uint32_t j = __umulhi(x, D->n_alias);
       const float ua = st.uniform();
       const uint4 a = D->alias[j];
-      const uint32_t v = ua < __uint_as_float(a.x) ? a.y : a.z;
-      const uint32_t nx = (uint32_t)D->nx;
-      const uint32_t nxy = nx * (uint32_t)D->ny;
-      const uint32_t iz = v / nxy;
-      const uint32_t r = v - iz * nxy;
-      const uint32_t iy = r / nx;
-      const uint32_t ix = r - iy * nx;
-      ox = ((float)ix + st.uniform()) * D->dx;
-      oy = ((float)iy + st.uniform()) * D->dy;
-      oz = ((float)iz + st.uniform()) * D->dz;
-      marsaglia(st, dx0, dy0, dz0);
+      const uint32_t c = ua < __uint_as_float(a.x) ? a.y : a.z;  // x | y << 10 | z << 20
+      const uint32_t ix = c & 1023u, iy = (c >> 10) & 1023u, iz = c >> 20;
+      o0 = ((float)ix + st.uniform()) * D->dx;
+      o1 = ((float)iy + st.uniform()) * D->dy;
+      o2 = ((float)iz + st.uniform()) * D->dz;
+      marsaglia(st, d0, d1, d2);
     }
+    sst[0][lane] = o0;
+    sst[1][lane] = o1;
+    sst[2][lane] = o2;
+    sst[3][lane] = d0;
+    sst[4][lane] = d1;
+    sst[5][lane] = d2;
     photon = 0;
     cnt = 0;
     h_steps = h_nulls = h_cr = h_pe_esc = 0;
     if (kDebug) h_esc = h_disc = 0.0;
     start_photon();
+    state = kFlight;
   };
 
-  // Score the history's merged deposit list: voxel sums S, S2 and the
-  // per-history organ scores.
+  // Score the history's merged deposits: voxel sums S, S2 and the
+  // per-history organ scores q_o = sum_{v in o} e_v c / (m_v N_o).
   auto flush_list = [&](bool final_flush) {
     const PhantomDesc *d = D;
     double edep = 0.0, sumv = 0.0;
-    for (uint32_t j = 0; j < cnt; ++j) {
+#pragma unroll
+    for (int i = 0; i < kRegDep; ++i) {
+      if ((uint32_t)i < cnt) {
+        atomicAdd(&d->tally[rv[i]].x, re[i]);
+        atomicAdd(&d->tally[rv[i]].y, re[i] * re[i]);
+        if (kDebug) {
+          edep += re[i];
+          sumv += (double)rv[i];
+        }
+      }
+    }
+    for (uint32_t j = kRegDep; j < cnt; ++j) {
       const uint32_t idx = j * L + gl;
       const uint32_t v = P.dep_v[idx];
       const double e = P.dep_e[idx];
@@ -190,30 +266,62 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
         sumv += (double)v;
       }
     }
-    if (d->label) {
-      // q_o = sum over the history's voxels of organ o of e_v c / (m_v N_o)
-      for (uint32_t j = 0; j < cnt; ++j) {
-        const uint32_t idx = j * L + gl;
-        const uint32_t v = P.dep_v[idx];
-        const uint32_t o = d->label[v];
-        const float rho = s_pal[d->rec[v]].w;
-        P.dep_v[idx] = o;
-        P.dep_e[idx] = P.dep_e[idx] * d->organ_w[o] / (double)rho;
-      }
-      for (uint32_t i = 0; i < cnt; ++i) {
-        const uint32_t ii = i * L + gl;
-        const uint32_t o = P.dep_v[ii];
-        if (o == 0 || o == 0xFFFFFFFFu) continue;
-        double q = P.dep_e[ii];
-        for (uint32_t j = i + 1; j < cnt; ++j) {
-          const uint32_t jj = j * L + gl;
-          if (P.dep_v[jj] == o) {
-            q += P.dep_e[jj];
-            P.dep_v[jj] = 0xFFFFFFFFu;
+    if (d->n_org > 0) {
+      if (cnt <= (uint32_t)kRegDep) {
+        // in place: the list registers turn into (organ, score) pairs
+#pragma unroll
+        for (int i = 0; i < kRegDep; ++i) {
+          const uint32_t oi = (uint32_t)i < cnt ? rr[i] >> 8 : 0u;
+          re[i] = oi ? re[i] * wl.w[oi] * s_irho[rr[i] & 0xFFu] : 0.0;
+          rr[i] = oi;
+        }
+#pragma unroll
+        for (int i = 0; i < kRegDep; ++i) {
+          bool first = rr[i] != 0;
+#pragma unroll
+          for (int k = 0; k < i; ++k) first = first && rr[k] != rr[i];
+          if (first) {
+            double s = re[i];
+#pragma unroll
+            for (int j = i + 1; j < kRegDep; ++j) s += rr[j] == rr[i] ? re[j] : 0.0;
+            atomicAdd(&wl.org[rr[i]].x, s);
+            atomicAdd(&wl.org[rr[i]].y, s * s);
           }
         }
-        atomicAdd(&s_org[wave][o].x, q);
-        atomicAdd(&s_org[wave][o].y, q * q);
+      } else {
+        // long history: move the register entries next to the overflow
+        // entries and merge organs over the whole list
+#pragma unroll
+        for (int i = 0; i < kRegDep; ++i) {
+          const uint32_t idx = (uint32_t)i * L + gl;
+          P.dep_v[idx] = rv[i];
+          P.dep_e[idx] = re[i];
+          P.dep_r[idx] = rr[i];
+        }
+        for (uint32_t j = 0; j < cnt; ++j) {
+          const uint32_t idx = j * L + gl;
+          const uint32_t r = P.dep_r[idx];
+          const uint32_t oo = r >> 8;
+          P.dep_v[idx] = oo;
+          P.dep_e[idx] = P.dep_e[idx] * wl.w[oo] * s_irho[r & 0xFFu];
+        }
+        unsigned long long used = 0ull;
+        for (uint32_t i = 0; i < cnt; ++i) {
+          if ((used >> i) & 1ull) continue;
+          const uint32_t ii = i * L + gl;
+          const uint32_t oo = P.dep_v[ii];
+          if (oo == 0) continue;
+          double s = P.dep_e[ii];
+          for (uint32_t j = i + 1; j < cnt; ++j) {
+            const uint32_t jj = j * L + gl;
+            if (P.dep_v[jj] == oo) {
+              s += P.dep_e[jj];
+              used |= 1ull << j;
+            }
+          }
+          atomicAdd(&wl.org[oo].x, s);
+          atomicAdd(&wl.org[oo].y, s * s);
+        }
       }
     }
     atomicAdd(&wa.stat[8], (unsigned long long)cnt);
@@ -234,34 +342,62 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
     cnt = 0;
   };
 
-  // Add energy e to voxel v in the history's deposit list (merged by voxel).
-  auto deposit = [&](uint32_t v, double e, int cause) {
-    atomicAdd(&wa.ledger[cause], e);
-    atomicAdd(&wa.stat[7], 1ull);
-    for (uint32_t j = 0; j < cnt; ++j) {
-      const uint32_t idx = j * L + gl;
-      if (P.dep_v[idx] == v) {
-        P.dep_e[idx] += e;
-        return;
+  // Add energy e to voxel v (record r16) in the history's deposit list,
+  // merged by voxel.  The registers hold the kRegDep most recent distinct
+  // voxels (a shift register, so no entry is addressed by a run-time
+  // index); older ones move to the lane's overflow list.
+  auto deposit = [&](uint32_t v, uint32_t r16, double e) {
+    bool found = false;
+#pragma unroll
+    for (int i = 0; i < kRegDep; ++i) {
+      const bool m = (uint32_t)i < cnt && rv[i] == v;
+      re[i] += m ? e : 0.0;
+      found = found || m;
+    }
+    if (found) return;
+    if (cnt > (uint32_t)kRegDep) {
+      for (uint32_t j = kRegDep; j < cnt; ++j) {
+        const uint32_t idx = j * L + gl;
+        if (P.dep_v[idx] == v) {
+          P.dep_e[idx] += e;
+          return;
+        }
       }
     }
     if (cnt == (uint32_t)kDepCap) {
+      // list full (not reached on the phantoms here; counted): score this
+      // deposit on its own, which splits the history's square for voxel v
       atomicAdd(&wa.stat[11], 1ull);
-      flush_list(false);
+      atomicAdd(&D->tally[v].x, e);
+      atomicAdd(&D->tally[v].y, e * e);
+      return;
     }
-    const uint32_t idx = cnt * L + gl;
-    P.dep_v[idx] = v;
-    P.dep_e[idx] = e;
+    if (cnt >= (uint32_t)kRegDep) {
+      const uint32_t idx = cnt * L + gl;
+      P.dep_v[idx] = rv[kRegDep - 1];
+      P.dep_e[idx] = re[kRegDep - 1];
+      P.dep_r[idx] = rr[kRegDep - 1];
+    }
+#pragma unroll
+    for (int i = kRegDep - 1; i > 0; --i) {
+      rv[i] = rv[i - 1];
+      re[i] = re[i - 1];
+      rr[i] = rr[i - 1];
+    }
+    rv[0] = v;
+    re[0] = e;
+    rr[0] = r16;
     ++cnt;
   };
 
-  for (;;) {
-    // ---- refill idle lanes from the wave's chunk, claiming chunks as needed
+  // Claim histories for the idle lanes from the wave's chunk, claiming new
+  // chunks (or switching phantom once the wave has drained) as needed.
+  auto refill = [&]() {
     for (;;) {
-      const unsigned long long need = __ballot(!alive);
+      const unsigned long long need = __ballot(state == kIdle);
       if (need == 0) break;
-      const bool any_alive = need != __ballot(1);
-      if (pend_p >= 0 && !any_alive) {
+      const bool any_busy = need != __ballot(1);
+      if (pend_p >= 0 && !any_busy) {
         // switch phantom once every lane of the wave has finished
         flush_wave();
         wp = pend_p;
@@ -270,15 +406,13 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
         cur_next = pend_next;
         cur_end = pend_end;
         pend_p = -1;
+        enter_phantom();
       }
       if (cur_next < cur_end) {
         const unsigned long long avail = cur_end - cur_next;
         const uint32_t nneed = __popcll(need);
         const uint32_t r = rank_in(need);
-        if (!alive && r < avail) {
-          start_history(cur_next + r);
-          alive = true;
-        }
+        if (state == kIdle && r < avail) start_history(cur_next + r);
         cur_next += nneed < avail ? nneed : avail;
         continue;
       }
@@ -312,121 +446,169 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(RunParams P) {
         pend_end = last;
       }
     }
-    if (__ballot(alive) == 0) {
-      if (pend_p >= 0) continue;
-      break;
-    }
-    if (!alive) continue;
+  };
 
-    // ---- one Woodcock step of this lane's photon
-    ++h_steps;
-    bool pdone = false;
-    {
-      const float s = -fast_log2(st.uniform()) * ep.inv_mu_ln2;
-      px += s * ux;
-      py += s * uy;
-      pz += s * uz;
-      const float fx = px * D->inv_dx, fy = py * D->inv_dy, fz = pz * D->inv_dz;
-      // written so that a NaN coordinate counts as outside
-      if (!(fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
-            fz < D->fnz)) {
-        atomicAdd(&wa.ledger[4], (double)E);
-        h_pe_esc += 0x10000u;
-        if (kDebug) h_esc += E;
-        pdone = true;
-      } else if (++psteps > kMaxPhotonSteps) {
-        // unreachable for valid input; bounds the loop for any input
-        atomicAdd(&wa.ledger[5], (double)E);
-        if (kDebug) h_disc += E;
-        pdone = true;
-      } else {
-        const uint32_t v =
-            (uint32_t)fx + (uint32_t)D->nx * ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz);
-        const float4 pal = s_pal[D->rec[v]];
-        const float mc = pal.x * ep.sig;
-        const float mpe = pal.y * ep.gpe;
-        const float mr = pal.z * ep.gr;
-        const float t = st.uniform() * ep.mu_hat;
-        int ev = t < mc ? 1 : (t < mc + mpe ? 2 : (t < mc + mpe + mr ? 3 : 0));
-        if (ev && !((P.mask >> (ev - 1)) & 1u)) ev = 0;
-        if (ev == 0) {
-          ++h_nulls;
-        } else {
-          ++n_real;
-          if (ev == 1) {
-            ++h_cr;
-            float cost;
-            const float eps = klein_nishina(st, E * (float)(1.0 / kMeC2), cost);
-            const float uphi = st.uniform();
-            const float e1 = eps * E;
-            deposit(v, (double)E - (double)e1, 1);
-            rotate(ux, uy, uz, cost, uphi);
-            E = e1;
-            if (E < P.cutoff) {
-              deposit(v, (double)E, 3);
-              pdone = true;
-            } else {
-              ep = energy_params(E, P.ln2_kn, D->ln2_major, P.l2emin, P.inv_dl2);
-            }
-          } else if (ev == 2) {
-            ++h_pe_esc;
-            deposit(v, (double)E, 2);
+  // Each pass runs one phase for the lanes in that phase's state: free
+  // flights by default, interactions or history turnover once enough lanes
+  // wait for them (or no lane can fly).  Gathering lanes by phase keeps the
+  // wave's lanes busy on the same code; every lane still consumes its own
+  // random stream in order, so results do not depend on the schedule.
+  for (;;) {
+    const uint32_t n_fly = __popcll(__ballot(state == kFlight));
+    const uint32_t n_int = __popcll(__ballot(state == kInteract));
+    const uint32_t n_end = __popcll(__ballot(state == kPhotonEnd));
+    // a waiting phase runs once it has phase_min lanes or outnumbers the flights
+    const bool go_int = n_int && (n_int >= P.phase_min || n_int >= n_fly);
+    const bool go_end = n_end && (n_end >= P.phase_min || n_end >= n_fly);
+    if (go_int && (!go_end || n_int >= n_end)) {
+      // ---- interactions at the collision points found by the flights
+      if (state == kInteract) {
+        ++n_real;
+        bool pdone = false;
+        double dep = -1.0;  // energy left in voxel ev_v by this event
+        if (ev_t == 1) {
+          ++h_cr;
+          float cost;
+          const float eps = klein_nishina(st, E * (float)(1.0 / kMeC2), cost);
+          const float uphi = st.uniform();
+          const float e1 = eps * E;
+          dep = (double)E - (double)e1;  // exact in FP64
+          atomicAdd(&wa.ledger[1], dep);
+          rotate(ux, uy, uz, cost, uphi);
+          E = e1;
+          if (E < P.cutoff) {
+            // the cutoff energy stays in the same voxel: T + E' = E
+            atomicAdd(&wa.ledger[3], (double)E);
+            atomicAdd(&wa.stat[7], 1ull);
+            dep += (double)E;
             pdone = true;
           } else {
-            h_cr += 0x10000u;
-            const float cost = thomson(st.uniform());
-            const float uphi = st.uniform();
-            rotate(ux, uy, uz, cost, uphi);
+            ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
           }
-          if (!pdone && P.max_real && n_real >= P.max_real) {
-            atomicAdd(&wa.ledger[5], (double)E);
-            if (kDebug) h_disc += E;
-            pdone = true;
+        } else if (ev_t == 2) {
+          ++h_pe_esc;
+          dep = (double)E;
+          atomicAdd(&wa.ledger[2], dep);
+          pdone = true;
+        } else {
+          h_cr += 0x10000u;
+          const float cost = thomson(st.uniform());
+          const float uphi = st.uniform();
+          rotate(ux, uy, uz, cost, uphi);
+        }
+        if (dep >= 0.0) {
+          atomicAdd(&wa.stat[7], 1ull);
+          deposit(ev_v, ev_r, dep);
+        }
+        if (!pdone && P.max_real && n_real >= P.max_real) {
+          atomicAdd(&wa.ledger[5], (double)E);
+          if (kDebug) h_disc += E;
+          pdone = true;
+        }
+        state = pdone ? kPhotonEnd : kFlight;
+      }
+      continue;
+    }
+    if (go_end) {
+      // ---- photon ends: start the second photon, or score the history
+      if (state == kPhotonEnd) {
+        if (photon + 1 < P.nph) {
+          ++photon;
+          start_photon();
+          state = kFlight;
+        } else {
+          atomicAdd(&wa.stat[0], 1ull);
+          atomicAdd(&wa.stat[1], (unsigned long long)P.nph);
+          atomicAdd(&wa.stat[2], (unsigned long long)h_steps);
+          atomicAdd(&wa.stat[3], (unsigned long long)h_nulls);
+          atomicAdd(&wa.stat[4], (unsigned long long)(h_cr & 0xFFFFu));
+          atomicAdd(&wa.stat[5], (unsigned long long)(h_pe_esc & 0xFFFFu));
+          atomicAdd(&wa.stat[6], (unsigned long long)(h_cr >> 16));
+          atomicAdd(&wa.stat[10], (unsigned long long)(h_pe_esc >> 16));
+          atomicAdd(&wa.stat[13], (unsigned long long)st.blk);
+          flush_list(true);
+          state = kIdle;
+        }
+      }
+      refill();
+      continue;
+    }
+    if (n_fly) {
+      // ---- one Woodcock step per flying photon
+      if (state == kFlight) {
+        ++h_steps;
+        st.reserve2();  // the step's two draws, refilled for all flying lanes at once
+        const float s = -fast_log2(st.take_uniform()) * ep.inv_mu_ln2;
+        px += s * ux;
+        py += s * uy;
+        pz += s * uz;
+        const float fx = px * D->inv_dx, fy = py * D->inv_dy, fz = pz * D->inv_dz;
+        // written so that a NaN coordinate counts as outside
+        if (!(fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
+              fz < D->fnz)) {
+          atomicAdd(&wa.ledger[4], (double)E);
+          h_pe_esc += 0x10000u;
+          if (kDebug) h_esc += E;
+          state = kPhotonEnd;
+        } else if (++psteps > kMaxPhotonSteps) {
+          // unreachable for valid input; bounds the loop for any input
+          atomicAdd(&wa.ledger[5], (double)E);
+          if (kDebug) h_disc += E;
+          state = kPhotonEnd;
+        } else {
+          const uint32_t v =
+              (uint32_t)fx + (uint32_t)D->nx * ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz);
+          const uint32_t r16 = D->rec[v];
+          const float4 pal = s_pal[r16 & 0xFFu];
+          const float mc = pal.x * ep.sig;
+          const float mpe = pal.y * ep.gpe;
+          const float mr = pal.z * ep.gr;
+          const float t = st.take_uniform() * ep.mu_hat;
+          int ev = t < mc ? 1 : (t < mc + mpe ? 2 : (t < mc + mpe + mr ? 3 : 0));
+          if (ev && !((P.mask >> (ev - 1)) & 1u)) ev = 0;
+          if (ev == 0) {
+            ++h_nulls;
+          } else {
+            ev_t = ev;
+            ev_v = v;
+            ev_r = r16;
+            state = kInteract;
           }
         }
       }
+      continue;
     }
-    if (pdone) {
-      if (photon + 1 < P.nph) {
-        ++photon;
-        start_photon();
-      } else {
-        atomicAdd(&wa.stat[0], 1ull);
-        atomicAdd(&wa.stat[1], (unsigned long long)P.nph);
-        atomicAdd(&wa.stat[2], (unsigned long long)h_steps);
-        atomicAdd(&wa.stat[3], (unsigned long long)h_nulls);
-        atomicAdd(&wa.stat[4], (unsigned long long)(h_cr & 0xFFFFu));
-        atomicAdd(&wa.stat[5], (unsigned long long)(h_pe_esc & 0xFFFFu));
-        atomicAdd(&wa.stat[6], (unsigned long long)(h_cr >> 16));
-        atomicAdd(&wa.stat[10], (unsigned long long)(h_pe_esc >> 16));
-        atomicAdd(&wa.stat[13], (unsigned long long)st.blk);
-        flush_list(true);
-        alive = false;
-      }
+    // no lane is flying or waiting: the wave is idle
+    refill();
+    if (__ballot(state != kIdle) == 0) {
+      if (pend_p >= 0) continue;
+      break;
     }
   }
   flush_wave();
 }
 
-int transport_occupancy_blocks_per_cu(bool debug) {
+int transport_occupancy_blocks_per_cu(bool debug, int n_slots) {
   int nb = 0;
-  hipError_t e = debug ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true>, kBlock, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false>, kBlock, 0);
+  const size_t dyn = transport_dyn_lds_bytes(n_slots);
+  hipError_t e = debug ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true>, kBlock, dyn)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false>, kBlock, dyn);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_t s) {
+  const size_t dyn = transport_dyn_lds_bytes(p.n_slots);
   if (debug)
-    hipLaunchKernelGGL(transport_kernel<true>, dim3(grid), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(transport_kernel<true>, dim3(grid), dim3(kBlock), dyn, s, p);
   else
-    hipLaunchKernelGGL(transport_kernel<false>, dim3(grid), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL(transport_kernel<false>, dim3(grid), dim3(kBlock), dyn, s, p);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Finalize: Eq. 1 per voxel
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void finalize_kernel(const uint8_t *__restrict__ rec,
+__global__ __launch_bounds__(256) void finalize_kernel(const uint16_t *__restrict__ rec,
                                                        const float4 *__restrict__ palette,
                                                        const double2 *__restrict__ tally,
                                                        uint64_t nvox, double n, double vkg,
@@ -435,7 +617,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const uint8_t *__restrict
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += stride) {
     const double2 t = tally[v];
-    const double rho = (double)palette[rec[v]].w;
+    const double rho = (double)palette[rec[v] & 0xFFu].w;
     const double cm = kJPerMeV / (rho * vkg);
     const double mean = t.x / n;
     rate[v] = mean * cm * a_ts;
@@ -451,7 +633,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const uint8_t *__restrict
   }
 }
 
-hipError_t launch_finalize(const uint8_t *rec, const float4 *palette, const double2 *tally,
+hipError_t launch_finalize(const uint16_t *rec, const float4 *palette, const double2 *tally,
                            uint64_t nvox, double n_decays, double vkg, double a_ts, double *rate,
                            double *rel, hipStream_t s) {
   uint64_t blocks = (nvox + 255) / 256;
@@ -482,8 +664,7 @@ __device__ __forceinline__ void voxel_rate(const double2 t, double rho, double n
   }
 }
 
-__global__ __launch_bounds__(256) void organ_kernel(const uint8_t *__restrict__ rec,
-                                                    const uint8_t *__restrict__ label,
+__global__ __launch_bounds__(256) void organ_kernel(const uint16_t *__restrict__ rec,
                                                     const float4 *__restrict__ palette,
                                                     const double2 *__restrict__ tally,
                                                     uint64_t nvox, int n_org, double n,
@@ -500,10 +681,11 @@ __global__ __launch_bounds__(256) void organ_kernel(const uint8_t *__restrict__ 
     uint32_t o = 0;
     double a = 0.0, b = 0.0;
     if (v < nvox) {
-      o = label[v];
+      const uint32_t r16 = rec[v];
+      o = r16 >> 8;
       if (o != 0 && (int)o <= n_org) {
         double r, e;
-        voxel_rate(tally[v], (double)palette[rec[v]].w, n, vkg, a_ts, r, e);
+        voxel_rate(tally[v], (double)palette[r16 & 0xFFu].w, n, vkg, a_ts, r, e);
         a = r;
         b = e * e;
       }
@@ -534,13 +716,13 @@ __global__ __launch_bounds__(256) void organ_kernel(const uint8_t *__restrict__ 
   }
 }
 
-hipError_t launch_organ_reduce(const uint8_t *rec, const uint8_t *label, const float4 *palette,
+hipError_t launch_organ_reduce(const uint16_t *rec, const float4 *palette,
                                const double2 *tally, uint64_t nvox, int n_org, double n_decays,
                                double vkg, double a_ts, double *acc, hipStream_t s) {
   uint64_t blocks = (nvox + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(organ_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, rec, label, palette,
+  hipLaunchKernelGGL(organ_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, rec, palette,
                      tally, nvox, n_org, n_decays, vkg, a_ts, acc);
   return hipGetLastError();
 }
@@ -594,7 +776,8 @@ hipError_t launch_debug_sample(int kind, float e_mev, uint64_t n, uint32_t s0, u
 }
 
 __global__ void debug_source_kernel(const uint4 *alias, uint32_t n_alias, uint32_t pid, uint64_t n,
-                                    uint32_t s0, uint32_t s1, uint32_t *out) {
+                                    uint32_t s0, uint32_t s1, uint32_t nx, uint32_t ny,
+                                    uint32_t *out) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   Stream<false> st;
@@ -603,15 +786,17 @@ __global__ void debug_source_kernel(const uint4 *alias, uint32_t n_alias, uint32
   const uint32_t j = __umulhi(x, n_alias);
   const float ua = st.uniform();
   const uint4 a = alias[j];
-  out[i] = ua < __uint_as_float(a.x) ? a.y : a.z;
+  const uint32_t c = ua < __uint_as_float(a.x) ? a.y : a.z;
+  out[i] = (c & 1023u) + nx * (((c >> 10) & 1023u) + ny * (c >> 20));
 }
 
 hipError_t launch_debug_source(const uint4 *alias, uint32_t n_alias, uint32_t pid, uint64_t n,
-                               uint32_t s0, uint32_t s1, uint32_t *out, hipStream_t s) {
+                               uint32_t s0, uint32_t s1, uint32_t nx, uint32_t ny, uint32_t *out,
+                               hipStream_t s) {
   const uint64_t blocks = (n + 255) / 256;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(debug_source_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, alias, n_alias,
-                     pid, n, s0, s1, out);
+                     pid, n, s0, s1, nx, ny, out);
   return hipGetLastError();
 }
 
