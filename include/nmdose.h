@@ -145,6 +145,34 @@ nmd_status nmd_set_activity(nmd_ctx *ctx, int32_t phantom_id, const float *activ
 nmd_status nmd_run_histories(nmd_ctx *ctx, int32_t phantom_id, uint64_t n_decays, uint64_t seed,
                              const nmd_run_opts *opts);
 
+/* Work-queue chunk (histories per claim) and workgroup count of the last
+ * nmd_run_histories launch.  With opts->chunk == 0 the chunk is tuned: the
+ * first run of a phantom set with at least 2^22 decays per phantom times a
+ * slice of itself with each candidate chunk and keeps the fastest (cached
+ * per context, and in the file named by NMD_TUNE_CACHE if set). */
+nmd_status nmd_get_last_launch(nmd_ctx *ctx, uint32_t *chunk, uint32_t *grid_blocks);
+
+/* ---- captured runs --------------------------------------------------------- */
+
+/* A HIP graph of one run of n_decays histories of phantom_id (-1 = all
+ * with activity) followed by the organ reduction of each labelled phantom
+ * and, if dose_rate_gy_s is given (single phantom), the Eq. 1 maps into
+ * the device buffers dose_rate_gy_s and rel_uncertainty (may be NULL).
+ * Each launch continues the phantoms' history streams exactly as
+ * nmd_run_histories would, so k launches equal one run of k * n_decays.
+ * The graph owns its own work-queue and deposit-list scratch.  It becomes
+ * invalid (NMD_E_STATE at launch) once any of its phantoms is registered
+ * again or gets a new activity map.  History records and the abort hook
+ * are not available in graphs. */
+typedef struct nmd_graph nmd_graph;
+nmd_status nmd_graph_create(nmd_ctx *ctx, int32_t phantom_id, uint64_t n_decays, uint64_t seed,
+                            const nmd_run_opts *opts, double *dose_rate_gy_s,
+                            double *rel_uncertainty, nmd_graph **out);
+/* Enqueue one replay on the context stream (asynchronous). */
+nmd_status nmd_graph_launch(nmd_graph *graph);
+/* Release the graph (waits for the context stream).  NULL is accepted. */
+void nmd_graph_destroy(nmd_graph *graph);
+
 /* Zero the tallies, ledger, statistics and history counter of a phantom
  * (-1 = all). */
 nmd_status nmd_reset_tallies(nmd_ctx *ctx, int32_t phantom_id);
@@ -166,6 +194,12 @@ nmd_status nmd_get_dose(nmd_ctx *ctx, int32_t phantom_id, double *dose_rate_gy_s
  * from per-history organ scores.  Synchronises the stream. */
 nmd_status nmd_get_organ_dose(nmd_ctx *ctx, int32_t phantom_id, int32_t n_organs,
                               double *dose_rate_gy_s, double *eps_eq3, double *rel_sigma_mean);
+
+/* Organ statistics from the last organ reduction enqueued for the phantom
+ * (by nmd_get_organ_dose or by a graph launch), without reducing again;
+ * same outputs as nmd_get_organ_dose.  Synchronises the stream. */
+nmd_status nmd_read_organ_dose(nmd_ctx *ctx, int32_t phantom_id, int32_t n_organs,
+                               double *dose_rate_gy_s, double *eps_eq3, double *rel_sigma_mean);
 
 /* Organ dose rate from the per-history organ scores (A * O_o / N), which
  * equals Eq. 2 up to rounding; host double[n_organs].  Synchronises. */

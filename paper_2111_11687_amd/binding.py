@@ -48,8 +48,9 @@ EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_run_opts_default", "nmd_set_phantom", "nmd_set_activity", "nmd_run_histories",
            "nmd_reset_tallies", "nmd_get_dose", "nmd_get_organ_dose", "nmd_get_organ_score",
            "nmd_get_ledger", "nmd_get_run_stats", "nmd_get_tallies", "nmd_set_tallies",
-           "nmd_debug_sample",
-           "nmd_debug_sample_source", "nmd_debug_xs")
+           "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
+           "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
+           "nmd_graph_launch", "nmd_graph_destroy")
 
 _lib = None
 
@@ -85,12 +86,20 @@ def load_library(path: str = LIB_PATH):
         "nmd_debug_sample": [vp, i32, d, u64, u64, vp],
         "nmd_debug_sample_source": [vp, i32, u64, u64, vp],
         "nmd_debug_xs": [vp, i32, u64, vp, vp],
+        "nmd_read_organ_dose": [vp, i32, i32, vp, vp, vp],
+        "nmd_get_last_launch": [vp, ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.POINTER(ctypes.c_uint32)],
+        "nmd_graph_create": [vp, i32, u64, u64, ctypes.POINTER(nmd_run_opts), vp, vp,
+                             ctypes.POINTER(vp)],
+        "nmd_graph_launch": [vp],
+        "nmd_graph_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int32
     L.nmd_destroy.restype = None
+    L.nmd_graph_destroy.restype = None
     L.nmd_run_opts_default.restype = None
     L.nmd_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -187,6 +196,41 @@ def nmd_get_organ_dose(ctx, phantom_id, n_organs):
     _check(ctx, load_library().nmd_get_organ_dose(ctx, int(phantom_id), int(n_organs), p(r),
                                                   p(e), p(s)))
     return r, e, s
+
+
+def nmd_read_organ_dose(ctx, phantom_id, n_organs):
+    """Results of the last organ reduction (e.g. one a graph ran)."""
+    r = np.zeros(n_organs)
+    e = np.zeros(n_organs)
+    s = np.zeros(n_organs)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    _check(ctx, load_library().nmd_read_organ_dose(ctx, int(phantom_id), int(n_organs), p(r),
+                                                   p(e), p(s)))
+    return r, e, s
+
+
+def nmd_get_last_launch(ctx):
+    ch, gr = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(ctx, load_library().nmd_get_last_launch(ctx, ctypes.byref(ch), ctypes.byref(gr)))
+    return int(ch.value), int(gr.value)
+
+
+def nmd_graph_create(ctx, phantom_id, n_decays, seed, opts=None, dose_rate=None,
+                     rel_uncertainty=None):
+    g = ctypes.c_void_p()
+    _check(ctx, load_library().nmd_graph_create(
+        ctx, int(phantom_id), int(n_decays), int(seed),
+        None if opts is None else ctypes.byref(opts), _dptr(dose_rate), _dptr(rel_uncertainty),
+        ctypes.byref(g)))
+    return g
+
+
+def nmd_graph_launch(ctx, graph):
+    _check(ctx, load_library().nmd_graph_launch(graph))
+
+
+def nmd_graph_destroy(graph):
+    load_library().nmd_graph_destroy(graph)
 
 
 def nmd_get_organ_score(ctx, phantom_id, n_organs):

@@ -61,6 +61,8 @@ struct Phantom {
   double dx = 0, dy = 0, dz = 0;  // cm
   uint64_t nvox = 0;
   DevBuf rec, alias, tally, organ, ledger, stats, major, organ_w;  // rec: u16 per voxel
+  DevBuf n_done_dev, organ_acc;      // device history counter; organ reduction output
+  uint64_t gen = 0;                  // changes whenever the device buffers change
   std::vector<int64_t> organ_count;  // voxels per label 0..n_org
   std::vector<uint8_t> used;         // palette entries present
   uint32_t n_alias = 0;
@@ -84,8 +86,13 @@ struct nmd_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   std::vector<PalEntry> pal;
-  DevBuf d_pal, d_kn, d_queue, d_desc, d_dep_v, d_dep_e, d_dep_r, d_acc;
+  DevBuf d_pal, d_kn, d_queue, d_desc, d_dep_v, d_dep_e, d_dep_r;
   uint32_t dep_lanes = 0;
+  std::string arch;                        // device name, for the tuner cache
+  std::map<std::string, uint32_t> tuned;   // work-queue chunk per phantom set
+  uint32_t last_chunk = 0, last_grid = 0;
+  hipStream_t capture = nullptr;           // stream used to capture graphs
+  uint64_t next_gen = 1;
   int cu_count = 0;
   float l2emin = 0, inv_dl2 = 0;
   uint32_t phase_min = 32;  // tuning: NMD_PHASE_MIN
@@ -192,6 +199,7 @@ nmd_status upload_desc(nmd_ctx *c, int32_t id, Phantom &p) {
   d.stats = p.stats.as<unsigned long long>();
   d.ln2_major = p.major.as<float>();
   d.organ_w = p.organ_w.as<double>();
+  d.n_done = p.n_done_dev.as<unsigned long long>();
   d.nx = p.nx;
   d.ny = p.ny;
   d.nz = p.nz;
@@ -217,6 +225,7 @@ nmd_status zero_tallies(nmd_ctx *c, Phantom &p) {
   HIP_TRY(c, launch_zero_bytes(p.organ.p, p.organ.n, c->stream));
   HIP_TRY(c, launch_zero_bytes(p.ledger.p, p.ledger.n, c->stream));
   HIP_TRY(c, launch_zero_bytes(p.stats.p, p.stats.n, c->stream));
+  HIP_TRY(c, launch_set_u64(p.n_done_dev.as<unsigned long long>(), 0ull, c->stream));
   p.n_done = 0;
   return NMD_OK;
 }
@@ -228,6 +237,213 @@ nmd_status to_host(nmd_ctx *c, std::vector<T> &h, const T *src, uint64_t n) {
   return sync(c);
 }
 
+
+// ---- runs ------------------------------------------------------------------
+constexpr uint32_t kTuneChunks[] = {128, 256, 512, 1024, 2048, 4096};
+constexpr uint64_t kTuneMinPerPhantom = 1ull << 22;
+
+struct RunPlan {
+  RunParams rp;
+  RunIds ids;
+  int grid = 0;
+  bool debug = false;
+  bool auto_chunk = false;  // caller asked for the tuned chunk
+  bool tuned = false;       // a tuned chunk was known
+  uint32_t abort_after = 0;
+  std::string key;          // tuner key: device and phantom shapes
+};
+
+std::string tune_key(nmd_ctx *c, const std::vector<int32_t> &ids) {
+  std::string k = c->arch;
+  char buf[64];
+  for (int32_t i : ids) {
+    const Phantom &p = c->ph[i];
+    snprintf(buf, sizeof buf, "|%dx%dx%d", p.nx, p.ny, p.nz);
+    k += buf;
+  }
+  return k;
+}
+
+void load_tune_cache(nmd_ctx *c) {
+  const char *path = std::getenv("NMD_TUNE_CACHE");
+  if (!path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char key[4096];
+  unsigned ch;
+  while (std::fscanf(f, "%4095s %u", key, &ch) == 2) c->tuned[key] = ch;
+  std::fclose(f);
+}
+
+void save_tune_cache(nmd_ctx *c) {
+  const char *path = std::getenv("NMD_TUNE_CACHE");
+  if (!path) return;
+  FILE *f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto &kv : c->tuned) std::fprintf(f, "%s %u\n", kv.first.c_str(), kv.second);
+  std::fclose(f);
+}
+
+// Split the run's histories into chunks of `chunk` for the work queue.
+void set_chunk(RunPlan &pl, uint64_t n, uint32_t chunk) {
+  pl.rp.chunk = chunk;
+  uint64_t total = 0;
+  for (int i = 0; i < pl.rp.n_ph; ++i) {
+    pl.rp.slot[i].n_hist = n;
+    pl.rp.slot[i].chunk0 = total;
+    total += (n + chunk - 1) / chunk;
+  }
+  pl.rp.total_chunks = total;
+}
+
+nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd_run_opts *opts_in,
+                    RunPlan &pl) {
+  nmd_run_opts o;
+  if (opts_in)
+    o = *opts_in;
+  else
+    nmd_run_opts_default(&o);
+  if (o.photons_per_decay < 1 || o.photons_per_decay > 2)
+    return fail(c, NMD_E_INVALID, "photons_per_decay must be 1 or 2");
+  if (o.process_mask > 7) return fail(c, NMD_E_INVALID, "process_mask must be <= 7");
+  if (!(o.photon_cutoff_mev >= 0.001f && o.photon_cutoff_mev <= 0.511f))
+    return fail(c, NMD_E_INVALID, "photon cutoff must lie in [0.001, 0.511] MeV");
+  if (o.source_kind > 1) return fail(c, NMD_E_INVALID, "source_kind must be 0 or 1");
+  float pd[3] = {o.pencil_dir[0], o.pencil_dir[1], o.pencil_dir[2]};
+  if (o.source_kind == 1) {
+    const double nn =
+        std::sqrt((double)pd[0] * pd[0] + (double)pd[1] * pd[1] + (double)pd[2] * pd[2]);
+    if (!(nn > 0) || !std::isfinite(nn)) return fail(c, NMD_E_INVALID, "pencil_dir must be nonzero");
+    for (int a = 0; a < 3; ++a) pd[a] = (float)(pd[a] / nn);
+  }
+  std::vector<int32_t> ids;
+  if (id == -1) {
+    for (auto &kv : c->ph)
+      if (kv.second.has_activity || o.source_kind == 1) ids.push_back(kv.first);
+    if (ids.empty()) return fail(c, NMD_E_STATE, "no phantom has an activity map");
+    if (o.history_records) return fail(c, NMD_E_INVALID, "history_records needs a single phantom");
+  } else {
+    Phantom *p = find(c, id);
+    if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+    if (o.source_kind == 0 && !p->has_activity)
+      return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
+    ids.push_back(id);
+  }
+  if (o.source_kind == 1) {
+    for (int32_t i : ids) {
+      const Phantom &p = c->ph[i];
+      const double L[3] = {p.nx * p.dx, p.ny * p.dy, p.nz * p.dz};
+      for (int a = 0; a < 3; ++a)
+        if (!(o.pencil_origin_cm[a] >= 0.0f && o.pencil_origin_cm[a] < L[a]))
+          return fail(c, NMD_E_INVALID, "pencil origin must lie inside the grid");
+    }
+  }
+  int n_slots = 1;
+  for (int32_t i : ids) n_slots = std::max(n_slots, c->ph[i].n_org + 1);
+  pl.debug = o.history_records != nullptr;
+  const int per_cu = transport_occupancy_blocks_per_cu(pl.debug, n_slots);
+  uint32_t grid = o.grid_blocks ? o.grid_blocks : (uint32_t)(c->cu_count * per_cu);
+  grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, 8192));
+  pl.grid = (int)grid;
+  const uint32_t lanes = grid * kBlock;
+  if (lanes > c->dep_lanes) {
+    nmd_status s;
+    if ((s = dev_alloc(c, c->d_dep_v, (size_t)lanes * kDepCap * sizeof(uint32_t))) ||
+        (s = dev_alloc(c, c->d_dep_e, (size_t)lanes * kDepCap * sizeof(double))) ||
+        (s = dev_alloc(c, c->d_dep_r, (size_t)lanes * kDepCap * sizeof(uint32_t)))) {
+      c->dep_lanes = 0;
+      return s;
+    }
+    c->dep_lanes = lanes;
+  }
+  pl.key = tune_key(c, ids);
+  pl.auto_chunk = o.chunk == 0;
+  uint32_t chunk = o.chunk;
+  if (chunk == 0) {
+    auto it = c->tuned.find(pl.key);
+    pl.tuned = it != c->tuned.end();
+    if (pl.tuned) {
+      chunk = it->second;
+    } else {
+      // enough claims per wave to balance, few enough to keep the queue cold
+      const uint64_t waves = (uint64_t)grid * kWavesPerBlock;
+      uint64_t ch = n * ids.size() / (waves * 16);
+      chunk = (uint32_t)std::max<uint64_t>(64, std::min<uint64_t>(ch, 4096));
+    }
+  }
+  RunParams &rp = pl.rp;
+  rp = RunParams{};
+  rp.desc = c->d_desc.as<PhantomDesc>();
+  rp.n_ph = (int32_t)ids.size();
+  pl.ids.n = (int32_t)ids.size();
+  for (size_t i = 0; i < ids.size(); ++i) {
+    rp.slot[i].id = ids[i];
+    pl.ids.id[i] = ids[i];
+  }
+  set_chunk(pl, n, chunk);
+  pl.abort_after = o.abort_after_chunks;
+  rp.abort_after = o.abort_after_chunks;
+  rp.seed_lo = (uint32_t)seed;
+  rp.seed_hi = (uint32_t)(seed >> 32);
+  rp.nph = o.source_kind == 1 ? 1u : o.photons_per_decay;
+  rp.mask = o.process_mask;
+  rp.max_real = o.max_real_events;
+  rp.cutoff = o.photon_cutoff_mev;
+  rp.source_kind = o.source_kind;
+  for (int a = 0; a < 3; ++a) {
+    rp.po[a] = o.pencil_origin_cm[a];
+    rp.pd[a] = pd[a];
+  }
+  rp.palette = c->d_pal.as<float4>();
+  rp.n_pal = (int32_t)c->pal.size();
+  rp.ln2_kn = c->d_kn.as<float>();
+  rp.l2emin = c->l2emin;
+  rp.inv_dl2 = c->inv_dl2;
+  rp.n_slots = n_slots;
+  rp.phase_min = c->phase_min;
+  rp.n_lanes = lanes;
+  rp.hist_rec = o.history_records;
+  return NMD_OK;
+}
+
+// Enqueue one run: clear the queue, transport, advance the history
+// counters.  Host mirrors of the counters advance at enqueue time.
+nmd_status enqueue_run(nmd_ctx *c, RunPlan &pl, unsigned long long *queue, uint32_t *dep_v,
+                       double *dep_e, uint32_t *dep_r, hipStream_t st) {
+  pl.rp.queue = queue;
+  pl.rp.dep_v = dep_v;
+  pl.rp.dep_e = dep_e;
+  pl.rp.dep_r = dep_r;
+  HIP_TRY(c, launch_zero_bytes(queue, 2 * sizeof(unsigned long long), st));
+  HIP_TRY(c, launch_transport(pl.rp, pl.grid, pl.debug, st));
+  uint64_t n = pl.rp.n_ph ? pl.rp.slot[0].n_hist : 0;
+  HIP_TRY(c, launch_advance(pl.rp.desc, pl.ids, n, st));
+  for (int i = 0; i < pl.ids.n; ++i) c->ph[pl.ids.id[i]].n_done += n;
+  return NMD_OK;
+}
+
+nmd_status enqueue_organ_reduce(nmd_ctx *c, Phantom &p, hipStream_t st) {
+  HIP_TRY(c, launch_zero_bytes(p.organ_acc.p, p.organ_acc.n, st));
+  HIP_TRY(c, launch_organ_reduce(p.rec.as<uint16_t>(), c->d_pal.as<float4>(),
+                                 p.tally.as<double2>(), p.nvox, p.n_org,
+                                 p.n_done_dev.as<unsigned long long>(), p.vkg(), p.a_ts,
+                                 p.organ_acc.as<double>(), st));
+  return NMD_OK;
+}
+
+}  // namespace
+
+struct nmd_graph {
+  nmd_ctx *c = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  RunIds ids = {};
+  uint64_t n = 0;
+  std::vector<uint64_t> gen;  // phantom generations when captured
+  DevBuf queue, dep_v, dep_e, dep_r;
+};
+
+namespace {
 }  // namespace
 
 // ============================================================================
@@ -267,6 +483,10 @@ nmd_status nmd_create(nmd_ctx **out, int device, void *stream) {
     return NMD_E_HIP;
   }
   c->cu_count = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  for (char &ch : c->arch)
+    if (ch == ' ' || ch == '|') ch = '_';
+  load_tune_cache(c);
   if (const char *e = std::getenv("NMD_PHASE_MIN")) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 1 && v <= 64) c->phase_min = (uint32_t)v;
@@ -279,8 +499,7 @@ nmd_status nmd_create(nmd_ctx **out, int device, void *stream) {
   if ((s = dev_alloc(c, c->d_kn, kNGrid * sizeof(float))) ||
       (s = dev_alloc(c, c->d_pal, kMaxPalette * sizeof(float4))) ||
       (s = dev_alloc(c, c->d_queue, 2 * sizeof(unsigned long long))) ||
-      (s = dev_alloc(c, c->d_desc, kMaxPhantoms * sizeof(PhantomDesc))) ||
-      (s = dev_alloc(c, c->d_acc, kMaxOrganSlots * 2 * sizeof(double)))) {
+      (s = dev_alloc(c, c->d_desc, kMaxPhantoms * sizeof(PhantomDesc)))) {
     delete c;
     return s;
   }
@@ -298,6 +517,7 @@ void nmd_destroy(nmd_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  if (c->capture) (void)hipStreamDestroy(c->capture);
   delete c;
 }
 
@@ -440,8 +660,11 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
       (s = dev_alloc(c, p.ledger, 8 * sizeof(double))) ||
       (s = dev_alloc(c, p.stats, 16 * sizeof(unsigned long long))) ||
       (s = dev_alloc(c, p.major, kNGrid * sizeof(float))) ||
-      (s = dev_alloc(c, p.organ_w, (n_organs + 1) * sizeof(double))))
+      (s = dev_alloc(c, p.organ_w, (n_organs + 1) * sizeof(double))) ||
+      (s = dev_alloc(c, p.n_done_dev, 2 * sizeof(unsigned long long))) ||
+      (s = dev_alloc(c, p.organ_acc, (n_organs + 1) * 2 * sizeof(double))))
     return s;
+  p.gen = c->next_gen++;
   HIP_TRY(c, hipMemcpyAsync(p.rec.p, rec.data(), nvox * sizeof(uint16_t), hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, hipMemcpyAsync(p.major.p, maj.data(), kNGrid * sizeof(float), hipMemcpyHostToDevice,
@@ -516,6 +739,7 @@ nmd_status nmd_set_activity(nmd_ctx *c, int32_t id, const float *act, double tot
   HIP_TRY(c, hipMemcpyAsync(d.p, tab.data(), n * sizeof(uint4), hipMemcpyHostToDevice, c->stream));
   if ((s = sync(c))) return s;
   p->alias = std::move(d);
+  p->gen = c->next_gen++;
   p->n_alias = (uint32_t)n;
   p->has_activity = true;
   p->a_ts = total_bq > 0.0 ? total_bq : sum * (p->dx * p->dy * p->dz);
@@ -540,119 +764,53 @@ nmd_status nmd_run_histories(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
                              const nmd_run_opts *opts_in) {
   nmd_status s = check_ctx(c);
   if (s) return s;
-  nmd_run_opts o;
-  if (opts_in)
-    o = *opts_in;
-  else
-    nmd_run_opts_default(&o);
-  if (o.photons_per_decay < 1 || o.photons_per_decay > 2)
-    return fail(c, NMD_E_INVALID, "photons_per_decay must be 1 or 2");
-  if (o.process_mask > 7) return fail(c, NMD_E_INVALID, "process_mask must be <= 7");
-  if (!(o.photon_cutoff_mev >= 0.001f && o.photon_cutoff_mev <= 0.511f))
-    return fail(c, NMD_E_INVALID, "photon cutoff must lie in [0.001, 0.511] MeV");
-  if (o.source_kind > 1) return fail(c, NMD_E_INVALID, "source_kind must be 0 or 1");
-  float pd[3] = {o.pencil_dir[0], o.pencil_dir[1], o.pencil_dir[2]};
-  if (o.source_kind == 1) {
-    const double nn = std::sqrt((double)pd[0] * pd[0] + (double)pd[1] * pd[1] + (double)pd[2] * pd[2]);
-    if (!(nn > 0) || !std::isfinite(nn)) return fail(c, NMD_E_INVALID, "pencil_dir must be nonzero");
-    for (int a = 0; a < 3; ++a) pd[a] = (float)(pd[a] / nn);
-    if (o.history_records && id == -1)
-      return fail(c, NMD_E_INVALID, "history_records needs a single phantom");
-  }
+  RunPlan plan;
+  if ((s = plan_run(c, id, n, seed, opts_in, plan))) return s;
   if (n == 0) return NMD_OK;
-
-  std::vector<int32_t> ids;
-  if (id == -1) {
-    for (auto &kv : c->ph)
-      if (kv.second.has_activity || o.source_kind == 1) ids.push_back(kv.first);
-    if (ids.empty()) return fail(c, NMD_E_STATE, "no phantom has an activity map");
-    if (o.history_records) return fail(c, NMD_E_INVALID, "history_records needs a single phantom");
-  } else {
-    Phantom *p = find(c, id);
-    if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
-    if (o.source_kind == 0 && !p->has_activity)
-      return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
-    ids.push_back(id);
-  }
-  if (o.source_kind == 1) {
-    for (int32_t i : ids) {
-      const Phantom &p = c->ph[i];
-      const double L[3] = {p.nx * p.dx, p.ny * p.dy, p.nz * p.dz};
-      for (int a = 0; a < 3; ++a)
-        if (!(o.pencil_origin_cm[a] >= 0.0f && o.pencil_origin_cm[a] < L[a]))
-          return fail(c, NMD_E_INVALID, "pencil origin must lie inside the grid");
-    }
-  }
-
-  // launch shape
-  int n_slots = 1;
-  for (int32_t i : ids) n_slots = std::max(n_slots, c->ph[i].n_org + 1);
-  const int per_cu = transport_occupancy_blocks_per_cu(o.history_records != nullptr, n_slots);
-  uint32_t grid = o.grid_blocks ? o.grid_blocks : (uint32_t)(c->cu_count * per_cu);
-  grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, 8192));
-  const uint32_t lanes = grid * kBlock;
-  if (lanes > c->dep_lanes) {
-    if ((s = dev_alloc(c, c->d_dep_v, (size_t)lanes * kDepCap * sizeof(uint32_t))) ||
-        (s = dev_alloc(c, c->d_dep_e, (size_t)lanes * kDepCap * sizeof(double))) ||
-        (s = dev_alloc(c, c->d_dep_r, (size_t)lanes * kDepCap * sizeof(uint32_t)))) {
-      c->dep_lanes = 0;
+  const bool tune = plan.auto_chunk && !plan.tuned && n >= kTuneMinPerPhantom;
+  if (!tune) {
+    if ((s = enqueue_run(c, plan, c->d_queue.as<unsigned long long>(), c->d_dep_v.as<uint32_t>(),
+                         c->d_dep_e.as<double>(), c->d_dep_r.as<uint32_t>(), c->stream)))
       return s;
+  } else {
+    // Tune the work-queue chunk on this run itself: a slice of it with each
+    // candidate, timed, then the rest with the fastest.  Histories continue
+    // across the slices, so the result is that of one launch.
+    const uint64_t slice = n / 16;
+    float best_ms = 0.0f;
+    uint32_t best = kTuneChunks[0];
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    uint64_t done = 0;
+    for (uint32_t ch : kTuneChunks) {
+      set_chunk(plan, slice, ch);
+      HIP_TRY(c, hipEventRecord(e0, c->stream));
+      if ((s = enqueue_run(c, plan, c->d_queue.as<unsigned long long>(), c->d_dep_v.as<uint32_t>(),
+                           c->d_dep_e.as<double>(), c->d_dep_r.as<uint32_t>(), c->stream)))
+        return s;
+      HIP_TRY(c, hipEventRecord(e1, c->stream));
+      HIP_TRY(c, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+      if (best_ms == 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best = ch;
+      }
+      done += slice;
     }
-    c->dep_lanes = lanes;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tuned[plan.key] = best;
+    save_tune_cache(c);
+    set_chunk(plan, n - done, best);
+    if ((s = enqueue_run(c, plan, c->d_queue.as<unsigned long long>(), c->d_dep_v.as<uint32_t>(),
+                         c->d_dep_e.as<double>(), c->d_dep_r.as<uint32_t>(), c->stream)))
+      return s;
   }
-  uint32_t chunk = o.chunk;
-  if (chunk == 0) {
-    // enough claims per wave to balance, few enough to keep the queue cold
-    const uint64_t waves = (uint64_t)grid * kWavesPerBlock;
-    uint64_t ch = n * ids.size() / (waves * 16);
-    ch = std::max<uint64_t>(64, std::min<uint64_t>(ch, 4096));
-    chunk = (uint32_t)ch;
-  }
-
-  RunParams rp = {};
-  rp.desc = c->d_desc.as<PhantomDesc>();
-  rp.n_ph = (int32_t)ids.size();
-  rp.chunk = chunk;
-  uint64_t total = 0;
-  for (size_t i = 0; i < ids.size(); ++i) {
-    Phantom &p = c->ph[ids[i]];
-    rp.slot[i].hid0 = p.n_done;
-    rp.slot[i].n_hist = n;
-    rp.slot[i].chunk0 = total;
-    rp.slot[i].id = ids[i];
-    total += (n + chunk - 1) / chunk;
-  }
-  rp.total_chunks = total;
-  rp.queue = c->d_queue.as<unsigned long long>();
-  rp.abort_after = o.abort_after_chunks;
-  rp.seed_lo = (uint32_t)seed;
-  rp.seed_hi = (uint32_t)(seed >> 32);
-  rp.nph = o.source_kind == 1 ? 1u : o.photons_per_decay;
-  rp.mask = o.process_mask;
-  rp.max_real = o.max_real_events;
-  rp.cutoff = o.photon_cutoff_mev;
-  rp.source_kind = o.source_kind;
-  for (int a = 0; a < 3; ++a) {
-    rp.po[a] = o.pencil_origin_cm[a];
-    rp.pd[a] = pd[a];
-  }
-  rp.palette = c->d_pal.as<float4>();
-  rp.n_pal = (int32_t)c->pal.size();
-  rp.ln2_kn = c->d_kn.as<float>();
-  rp.l2emin = c->l2emin;
-  rp.inv_dl2 = c->inv_dl2;
-  rp.dep_v = c->d_dep_v.as<uint32_t>();
-  rp.dep_e = c->d_dep_e.as<double>();
-  rp.dep_r = c->d_dep_r.as<uint32_t>();
-  rp.n_slots = n_slots;
-  rp.phase_min = c->phase_min;
-  rp.n_lanes = lanes;
-  rp.hist_rec = o.history_records;
-
-  HIP_TRY(c, launch_zero_bytes(c->d_queue.p, c->d_queue.n, c->stream));
-  HIP_TRY(c, launch_transport(rp, (int)grid, o.history_records != nullptr, c->stream));
-  for (int32_t i : ids) c->ph[i].n_done += n;
-  if (o.abort_after_chunks) {
+  c->last_chunk = plan.rp.chunk;
+  c->last_grid = (uint32_t)plan.grid;
+  if (plan.abort_after) {
     unsigned long long q[2] = {0, 0};
     HIP_TRY(c, hipMemcpyAsync(q, c->d_queue.p, sizeof q, hipMemcpyDeviceToHost, c->stream));
     if ((s = sync(c))) return s;
@@ -670,7 +828,41 @@ nmd_status nmd_get_dose(nmd_ctx *c, int32_t id, double *rate, double *rel) {
     return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
   if (!rate) return fail(c, NMD_E_INVALID, "dose_rate buffer is required");
   HIP_TRY(c, launch_finalize(p->rec.as<uint16_t>(), c->d_pal.as<float4>(), p->tally.as<double2>(),
-                             p->nvox, (double)p->n_done, p->vkg(), p->a_ts, rate, rel, c->stream));
+                             p->nvox, p->n_done_dev.as<unsigned long long>(), p->vkg(), p->a_ts,
+                             rate, rel, c->stream));
+  return NMD_OK;
+}
+
+nmd_status nmd_read_organ_dose(nmd_ctx *c, int32_t id, int32_t n_organs, double *rate,
+                               double *eps3, double *sig_mean) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->has_label) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
+  if (!p->has_activity || p->n_done == 0)
+    return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
+  if (n_organs < 0 || n_organs > p->n_org)
+    return fail(c, NMD_E_INVALID, "n_organs %d exceeds the phantom's %d", n_organs, p->n_org);
+  const double n = (double)p->n_done;
+  std::vector<double> acc((p->n_org + 1) * 2);
+  std::vector<double2> org(p->n_org + 1);
+  HIP_TRY(c, hipMemcpyAsync(acc.data(), p->organ_acc.p, acc.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(org.data(), p->organ.p, org.size() * sizeof(double2),
+                            hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c))) return s;
+  for (int o = 1; o <= n_organs; ++o) {
+    const double cnt = (double)p->organ_count[o];
+    if (rate) rate[o - 1] = cnt > 0 ? acc[2 * o] / cnt : 0.0;
+    if (eps3) eps3[o - 1] = cnt > 0 ? std::sqrt(acc[2 * o + 1] / cnt) : 0.0;
+    if (sig_mean) {
+      const double m = org[o].x / n;
+      double var = n > 1 ? (org[o].y / n - m * m) / (n - 1.0) : 0.0;
+      if (var < 0) var = 0;
+      sig_mean[o - 1] = m > 0 ? std::sqrt(var) / m : 0.0;
+    }
+  }
   return NMD_OK;
 }
 
@@ -683,37 +875,8 @@ nmd_status nmd_get_organ_dose(nmd_ctx *c, int32_t id, int32_t n_organs, double *
   if (!p->has_label) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
   if (!p->has_activity || p->n_done == 0)
     return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
-  if (n_organs < 0 || n_organs > p->n_org)
-    return fail(c, NMD_E_INVALID, "n_organs %d exceeds the phantom's %d", n_organs, p->n_org);
-  const double n = (double)p->n_done;
-  if (rate || eps3) {
-    HIP_TRY(c, launch_zero_bytes(c->d_acc.p, (p->n_org + 1) * 2 * sizeof(double), c->stream));
-    HIP_TRY(c, launch_organ_reduce(p->rec.as<uint16_t>(), c->d_pal.as<float4>(), p->tally.as<double2>(), p->nvox,
-                                   p->n_org, n, p->vkg(), p->a_ts, c->d_acc.as<double>(),
-                                   c->stream));
-    std::vector<double> acc((p->n_org + 1) * 2);
-    HIP_TRY(c, hipMemcpyAsync(acc.data(), c->d_acc.p, acc.size() * sizeof(double),
-                              hipMemcpyDeviceToHost, c->stream));
-    if ((s = sync(c))) return s;
-    for (int o = 1; o <= n_organs; ++o) {
-      const double cnt = (double)p->organ_count[o];
-      if (rate) rate[o - 1] = cnt > 0 ? acc[2 * o] / cnt : 0.0;
-      if (eps3) eps3[o - 1] = cnt > 0 ? std::sqrt(acc[2 * o + 1] / cnt) : 0.0;
-    }
-  }
-  if (sig_mean) {
-    std::vector<double2> org(p->n_org + 1);
-    HIP_TRY(c, hipMemcpyAsync(org.data(), p->organ.p, org.size() * sizeof(double2),
-                              hipMemcpyDeviceToHost, c->stream));
-    if ((s = sync(c))) return s;
-    for (int o = 1; o <= n_organs; ++o) {
-      const double m = org[o].x / n;
-      double var = n > 1 ? (org[o].y / n - m * m) / (n - 1.0) : 0.0;
-      if (var < 0) var = 0;
-      sig_mean[o - 1] = m > 0 ? std::sqrt(var) / m : 0.0;
-    }
-  }
-  return NMD_OK;
+  if ((s = enqueue_organ_reduce(c, *p, c->stream))) return s;
+  return nmd_read_organ_dose(c, id, n_organs, rate, eps3, sig_mean);
 }
 
 nmd_status nmd_get_organ_score(nmd_ctx *c, int32_t id, int32_t n_organs, double *rate) {
@@ -792,8 +955,107 @@ nmd_status nmd_set_tallies(nmd_ctx *c, int32_t id, const double *sum, const doub
   HIP_TRY(c, hipMemcpy2DAsync(p->tally.as<char>() + sizeof(double), sizeof(double2), sum2,
                               sizeof(double), sizeof(double), p->nvox, hipMemcpyDefault,
                               c->stream));
+  HIP_TRY(c, launch_set_u64(p->n_done_dev.as<unsigned long long>(), n, c->stream));
   p->n_done = n;
   return sync(c);
+}
+
+nmd_status nmd_get_last_launch(nmd_ctx *c, uint32_t *chunk, uint32_t *grid_blocks) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  if (chunk) *chunk = c->last_chunk;
+  if (grid_blocks) *grid_blocks = c->last_grid;
+  return NMD_OK;
+}
+
+nmd_status nmd_graph_create(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
+                            const nmd_run_opts *opts, double *dose_rate, double *rel_unc,
+                            nmd_graph **out) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  if (!out) return fail(c, NMD_E_INVALID, "out is required");
+  *out = nullptr;
+  if (n == 0) return fail(c, NMD_E_INVALID, "n_decays must be > 0");
+  if (opts && (opts->history_records || opts->abort_after_chunks))
+    return fail(c, NMD_E_INVALID, "history records and the abort hook are not captured");
+  if (dose_rate && id == -1) return fail(c, NMD_E_INVALID, "dose maps need a single phantom");
+  RunPlan plan;
+  if ((s = plan_run(c, id, n, seed, opts, plan))) return s;
+  nmd_graph *g = new nmd_graph();
+  g->c = c;
+  g->ids = plan.ids;
+  g->n = n;
+  const size_t lanes = (size_t)plan.rp.n_lanes;
+  if ((s = dev_alloc(c, g->queue, 2 * sizeof(unsigned long long))) ||
+      (s = dev_alloc(c, g->dep_v, lanes * kDepCap * sizeof(uint32_t))) ||
+      (s = dev_alloc(c, g->dep_e, lanes * kDepCap * sizeof(double))) ||
+      (s = dev_alloc(c, g->dep_r, lanes * kDepCap * sizeof(uint32_t)))) {
+    delete g;
+    return s;
+  }
+  if (!c->capture && hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return fail(c, NMD_E_HIP, "cannot create the capture stream");
+  }
+  // the host counters must not move during capture: restore them after
+  std::vector<uint64_t> done(plan.ids.n);
+  for (int i = 0; i < plan.ids.n; ++i) done[i] = c->ph[plan.ids.id[i]].n_done;
+  hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = enqueue_run(c, plan, g->queue.as<unsigned long long>(), g->dep_v.as<uint32_t>(),
+                    g->dep_e.as<double>(), g->dep_r.as<uint32_t>(), c->capture);
+    if (!s && dose_rate) {
+      Phantom &p = c->ph[id];
+      e = launch_finalize(p.rec.as<uint16_t>(), c->d_pal.as<float4>(), p.tally.as<double2>(),
+                          p.nvox, p.n_done_dev.as<unsigned long long>(), p.vkg(), p.a_ts,
+                          dose_rate, rel_unc, c->capture);
+    }
+    for (int i = 0; !s && e == hipSuccess && i < plan.ids.n; ++i) {
+      Phantom &p = c->ph[plan.ids.id[i]];
+      if (p.has_label) s = enqueue_organ_reduce(c, p, c->capture);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->capture, &graph);
+    if (e == hipSuccess) e = e2;
+    g->g = graph;
+  }
+  for (int i = 0; i < plan.ids.n; ++i) c->ph[plan.ids.id[i]].n_done = done[i];
+  if (!s && e == hipSuccess) e = hipGraphInstantiate(&g->ge, g->g, nullptr, nullptr, 0);
+  if (s || e != hipSuccess) {
+    if (g->ge) (void)hipGraphExecDestroy(g->ge);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    delete g;
+    if (s) return s;
+    return fail(c, NMD_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  for (int i = 0; i < plan.ids.n; ++i) g->gen.push_back(c->ph[plan.ids.id[i]].gen);
+  *out = g;
+  return NMD_OK;
+}
+
+nmd_status nmd_graph_launch(nmd_graph *g) {
+  if (!g) return NMD_E_INVALID;
+  nmd_ctx *c = g->c;
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  for (int i = 0; i < g->ids.n; ++i) {
+    Phantom *p = find(c, g->ids.id[i]);
+    if (!p || p->gen != g->gen[i])
+      return fail(c, NMD_E_STATE, "phantom %d changed since the graph was captured",
+                  g->ids.id[i]);
+  }
+  HIP_TRY(c, hipGraphLaunch(g->ge, c->stream));
+  for (int i = 0; i < g->ids.n; ++i) c->ph[g->ids.id[i]].n_done += g->n;
+  return NMD_OK;
+}
+
+void nmd_graph_destroy(nmd_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->c->device);
+  if (g->c->stream) (void)hipStreamSynchronize(g->c->stream);
+  if (g->ge) (void)hipGraphExecDestroy(g->ge);
+  if (g->g) (void)hipGraphDestroy(g->g);
+  delete g;
 }
 
 nmd_status nmd_debug_sample(nmd_ctx *c, int32_t kind, double e_mev, uint64_t n, uint64_t seed,

@@ -46,6 +46,7 @@ struct PhantomDesc {
   unsigned long long *stats; // [kStatN]
   const float *ln2_major;    // [kNGrid] log2 of majorant nodes, cm^-1
   const double *organ_w;     // [n_org+1] c / (V[cm^3] 1e-3 N_o), J/MeV per kg*(g/cm^3)
+  unsigned long long *n_done;  // decays run since the last reset (next history id)
   int32_t nx, ny, nz, n_org;
   float fnx, fny, fnz;
   float dx, dy, dz, inv_dx, inv_dy, inv_dz;
@@ -55,11 +56,16 @@ struct PhantomDesc {
 
 // Per-run fields of one phantom of a launch.
 struct RunSlot {
-  unsigned long long hid0;    // first history id of this run
   unsigned long long n_hist;  // histories in this run
   unsigned long long chunk0;  // first work-queue chunk of this phantom
   int32_t id;                 // index into the descriptor array
   int32_t pad;
+};
+
+// Phantom ids of one run (for the counter update after it).
+struct RunIds {
+  int32_t n;
+  int32_t id[kMaxPhantoms];
 };
 
 struct RunParams {
@@ -94,10 +100,12 @@ hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_
 int transport_occupancy_blocks_per_cu(bool debug, int n_slots);
 size_t transport_dyn_lds_bytes(int n_slots);
 hipError_t launch_finalize(const uint16_t *rec, const float4 *palette, const double2 *tally,
-                           uint64_t nvox, double n_decays, double voxel_kg_per_rho,
+                           uint64_t nvox, const unsigned long long *n_decays,
+                           double voxel_kg_per_rho,
                            double a_ts, double *rate, double *rel, hipStream_t s);
 hipError_t launch_organ_reduce(const uint16_t *rec, const float4 *palette,
-                               const double2 *tally, uint64_t nvox, int n_org, double n_decays,
+                               const double2 *tally, uint64_t nvox, int n_org,
+                               const unsigned long long *n_decays,
                                double voxel_kg_per_rho, double a_ts,
                                double *acc /* [(n_org+1)*2] */, hipStream_t s);
 hipError_t launch_debug_sample(int kind, float e_mev, uint64_t n, uint32_t seed_lo,
@@ -110,5 +118,8 @@ hipError_t launch_debug_xs(const float4 *palette, const uint8_t *used, int n_pal
                            const float *energies, float *out, float l2emin, float inv_dl2,
                            hipStream_t s);
 hipError_t launch_zero_bytes(void *p, uint64_t nbytes, hipStream_t s);
+hipError_t launch_advance(const PhantomDesc *desc, const RunIds &ids, unsigned long long n,
+                          hipStream_t s);
+hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
 
 }  // namespace nmd

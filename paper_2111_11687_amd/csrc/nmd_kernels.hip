@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         flush_wave();
         wp = pend_p;
         D = P.desc + P.slot[wp].id;
-        hid0 = P.slot[wp].hid0;
+        hid0 = *D->n_done;  // histories already run on this phantom
         cur_next = pend_next;
         cur_end = pend_end;
         pend_p = -1;
@@ -611,10 +611,13 @@ hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_
 __global__ __launch_bounds__(256) void finalize_kernel(const uint16_t *__restrict__ rec,
                                                        const float4 *__restrict__ palette,
                                                        const double2 *__restrict__ tally,
-                                                       uint64_t nvox, double n, double vkg,
+                                                       uint64_t nvox,
+                                                       const unsigned long long *__restrict__ n_done,
+                                                       double vkg,
                                                        double a_ts, double *__restrict__ rate,
                                                        double *__restrict__ rel) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const double n = (double)*n_done;
   for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += stride) {
     const double2 t = tally[v];
     const double rho = (double)palette[rec[v] & 0xFFu].w;
@@ -634,7 +637,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(const uint16_t *__restric
 }
 
 hipError_t launch_finalize(const uint16_t *rec, const float4 *palette, const double2 *tally,
-                           uint64_t nvox, double n_decays, double vkg, double a_ts, double *rate,
+                           uint64_t nvox, const unsigned long long *n_decays, double vkg,
+                           double a_ts, double *rate,
                            double *rel, hipStream_t s) {
   uint64_t blocks = (nvox + 255) / 256;
   if (blocks > 8192) blocks = 8192;
@@ -667,13 +671,15 @@ __device__ __forceinline__ void voxel_rate(const double2 t, double rho, double n
 __global__ __launch_bounds__(256) void organ_kernel(const uint16_t *__restrict__ rec,
                                                     const float4 *__restrict__ palette,
                                                     const double2 *__restrict__ tally,
-                                                    uint64_t nvox, int n_org, double n,
+                                                    uint64_t nvox, int n_org,
+                                                    const unsigned long long *__restrict__ n_done,
                                                     double vkg, double a_ts,
                                                     double *__restrict__ out) {
   __shared__ double2 s_acc[kMaxOrganSlots];
   for (int i = threadIdx.x; i < kMaxOrganSlots; i += 256) s_acc[i] = make_double2(0.0, 0.0);
   __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const double n = (double)*n_done;
   const uint64_t nround = (nvox + stride - 1) / stride;
   uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = lane_id();
@@ -717,7 +723,8 @@ __global__ __launch_bounds__(256) void organ_kernel(const uint16_t *__restrict__
 }
 
 hipError_t launch_organ_reduce(const uint16_t *rec, const float4 *palette,
-                               const double2 *tally, uint64_t nvox, int n_org, double n_decays,
+                               const double2 *tally, uint64_t nvox, int n_org,
+                               const unsigned long long *n_decays,
                                double vkg, double a_ts, double *acc, hipStream_t s) {
   uint64_t blocks = (nvox + 255) / 256;
   if (blocks > 4096) blocks = 4096;
@@ -826,6 +833,25 @@ hipError_t launch_debug_xs(const float4 *palette, const uint8_t *used, int n_pal
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(debug_xs_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, palette, used,
                      n_pal, ln2_kn, ln2_major, n, energies, out, l2emin, inv_dl2);
+  return hipGetLastError();
+}
+
+// After a run: advance the history counters of the phantoms it covered.
+__global__ void advance_kernel(const PhantomDesc *desc, RunIds ids, unsigned long long n) {
+  const int i = threadIdx.x;
+  if (i < ids.n) *desc[ids.id[i]].n_done += n;
+}
+
+hipError_t launch_advance(const PhantomDesc *desc, const RunIds &ids, unsigned long long n,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(kMaxPhantoms), 0, s, desc, ids, n);
+  return hipGetLastError();
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v) { *p = v; }
+
+hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(1), 0, s, p, v);
   return hipGetLastError();
 }
 
