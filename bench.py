@@ -79,10 +79,11 @@ def main():
     ap.add_argument("--decays-per-step", type=int, default=10 ** 8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("patient", "batch64"), default="patient",
+    ap.add_argument("--workload", choices=("patient", "batch64", "denoiser"), default="patient",
                     help="patient: the 256x256x320 phantom (the headline metric); batch64: 64 "
                          "uneven phantoms, 10^7 decays each per step, one graph-captured "
-                         "launch per step with the autotuned chunk")
+                         "launch per step with the autotuned chunk; denoiser: U-Net training "
+                         "steps on 128x128x160 boxes and inference on the whole phantom")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy, to scale the "
                          "HBM byte counters of a profile against a known size")
@@ -104,6 +105,8 @@ def main():
         del a, b
     if args.workload == "batch64":
         return bench_batch(args)
+    if args.workload == "denoiser":
+        return bench_denoiser(args)
     prob = P.patient_phantom()
     eng = B.Engine(0)
     eng.set_problem(0, prob)
@@ -227,6 +230,118 @@ def bench_batch(args):
     }
     eng.close()
     print(json.dumps(out), flush=True)
+
+
+# MI355X dense BF16 matrix-core peak (no sparsity)
+MFMA_BF16_PEAK = 2.5e15
+
+
+def cpu_baseline_denoiser(target_s):
+    """The CPU oracle (FP64 U-Net forward and backward) on small boxes."""
+    import torch
+    from oracle import unet as U
+    threads = torch.get_num_threads()
+    p = U.init_params(width=16, seed=1)
+    p["head.w"] = torch.full((16,), 0.1)
+    shape = (16, 32, 32)
+    g = torch.Generator().manual_seed(3)
+    x0 = torch.rand((1,) + shape + (3,), generator=g, dtype=torch.float64)
+    tgt = torch.rand((1,) + shape, generator=g, dtype=torch.float64)
+    from paper_2111_11687_amd import denoiser as DN
+    flops = 3 * DN.conv_flops(shape)  # forward + backward-data + backward-weight
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < target_s:
+        U.loss_and_grads(p, x0, tgt, bf16_storage=True)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n * flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d FP64 training passes on 16x32x32 boxes, %.1f s" % (n, dt)}
+
+
+def bench_denoiser(args):
+    """U-Net training steps (forward, loss, backward, Adam) on 128x128x160
+    boxes of the patient phantom, then inference on the whole phantom."""
+    import torch
+    from paper_2111_11687_amd import binding as B
+    from paper_2111_11687_amd import denoiser as DN
+    from paper_2111_11687_amd import phantoms as P
+
+    prob = P.patient_phantom()
+    eng = B.Engine(0)
+    eng.set_problem(0, prob)
+    eng.run(0, 10 ** 7, 1000103)
+    lo, _ = eng.dose(0)
+    B.nmd_reset_tallies(eng.ctx, 0)
+    eng.run(0, 10 ** 8, 2000103)
+    hi, _ = eng.dose(0)
+    inp = eng.inputs[0]
+    box_shape = (160, 128, 128)
+    box = (80, 64, 64) + box_shape
+    net = DN.UNet(eng, seed=1)
+    net.p["head.w"].fill_(0.05)  # non-zero head so every layer carries gradient
+    ws = DN.Workspace(eng, box_shape)
+    ws.prepare(eng, prob.shape, box, lo, inp["density"], inp["activity"], inp["label"], hi)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        net.train_step(ws)
+    torch.cuda.synchronize()
+    evs = {}
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in step_ev:
+        a.record(stream)
+        net.train_step(ws, events=evs)
+        b.record(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    loss = ws.loss_value(net)
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b in step_ev]))
+    layer_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in evs.items()}
+    train_flops = 3 * DN.conv_flops(box_shape)
+    # dominant kernel: the level-0 decoder convolution 48 -> 16 channels
+    d, h, w = box_shape
+    dom_flops = 2 * 27 * 48 * 16 * d * h * w
+    dom_ms = layer_ms["dec0a"]
+    # inference on the whole phantom
+    wsf = DN.Workspace(eng, prob.shape, train=False)
+    out = torch.empty(prob.shape, dtype=torch.float64, device="cuda")
+    wsf.prepare(eng, prob.shape, (0, 0, 0) + tuple(prob.shape), lo, inp["density"],
+                inp["activity"], inp["label"])
+    net.predict(wsf, out)
+    torch.cuda.synchronize()
+    inf_ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    inf_ev[0].record(stream)
+    net.predict(wsf, out)
+    inf_ev[1].record(stream)
+    torch.cuda.synchronize()
+    inf_ms = inf_ev[0].elapsed_time(inf_ev[1])
+    inf_flops = DN.conv_flops(prob.shape)
+    print(json.dumps({"loss": loss, "layer_forward_ms": layer_ms, "step_ms": step_ms,
+                      "inference_full_phantom_ms": inf_ms,
+                      "inference_tflops": inf_flops / (inf_ms * 1e-3) / 1e12}), file=sys.stderr)
+    res = {
+        "metric": "denoiser training throughput (U-Net steps on 128x128x160 boxes)",
+        "value": args.steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "3D U-Net 16/32/64 channels, 3 levels, boxes of 160x128x128 "
+                               "voxels of the patient phantom (inputs from 10^7 decays, "
+                               "targets from 10^8)",
+                   "train_tflop_per_step": train_flops / 1e12,
+                   "train_tflops": train_flops / (step_ms * 1e-3) / 1e12,
+                   "inference_full_phantom_ms": inf_ms},
+        "roofline": {"bound": "mfma", "achieved": dom_flops / (dom_ms * 1e-3) / 1e12,
+                     "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": dom_flops / (dom_ms * 1e-3) / MFMA_BF16_PEAK, "traffic": None,
+                     "kernel": "conv_kernel<16,1> (dec0a forward, 48->16 channels)",
+                     "kernel_ms": dom_ms},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_denoiser(min(args.cpu_seconds, 15.0))
+    eng.close()
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

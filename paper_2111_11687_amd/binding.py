@@ -1,4 +1,5 @@
-"""Thin ctypes binding of ``libnmdose.so`` (the C ABI in include/nmdose.h).
+"""Thin ctypes binding of ``libnmdose.so`` (the C ABI in include/nmdose.h and
+include/nmdose_nn.h).
 
 Every ``nmd_*`` function here marshals its arguments and calls the C entry
 point of the same name; all computation runs in the HIP kernels.  PyTorch is
@@ -44,13 +45,22 @@ class nmd_run_opts(ctypes.Structure):
                 ("history_records", ctypes.c_void_p)]
 
 
+class nmd_nn_src(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_void_p), ("c0", ctypes.c_int32), ("up0", ctypes.c_int32),
+                ("x1", ctypes.c_void_p), ("c1", ctypes.c_int32)]
+
+
+NN_EXPORTS = ("nmd_conv3d_fwd", "nmd_conv3d_bwd_data", "nmd_conv3d_bwd_weight", "nmd_nn_pool2",
+              "nmd_nn_combine", "nmd_nn_prepare", "nmd_nn_head_loss", "nmd_nn_head_infer",
+              "nmd_nn_adam", "nmd_nn_cast_weight", "nmd_organ_mean_map", "nmd_debug_mfma")
+
 EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_run_opts_default", "nmd_set_phantom", "nmd_set_activity", "nmd_run_histories",
            "nmd_reset_tallies", "nmd_get_dose", "nmd_get_organ_dose", "nmd_get_organ_score",
            "nmd_get_ledger", "nmd_get_run_stats", "nmd_get_tallies", "nmd_set_tallies",
            "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
            "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
-           "nmd_graph_launch", "nmd_graph_destroy")
+           "nmd_graph_launch", "nmd_graph_destroy") + NN_EXPORTS
 
 _lib = None
 
@@ -93,6 +103,22 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(vp)],
         "nmd_graph_launch": [vp],
         "nmd_graph_destroy": [vp],
+        "nmd_conv3d_fwd": [vp, i32, i32, i32, i32, ctypes.POINTER(nmd_nn_src), vp, vp, i32, i32,
+                           vp, vp],
+        "nmd_conv3d_bwd_data": [vp, i32, i32, i32, i32, vp, i32, vp, i32, vp, vp],
+        "nmd_conv3d_bwd_weight": [vp, i32, i32, i32, i32, ctypes.POINTER(nmd_nn_src), vp, i32,
+                                  vp, vp],
+        "nmd_nn_pool2": [vp, i32, i32, i32, i32, i32, vp, vp],
+        "nmd_nn_combine": [vp, i32, i32, i32, i32, i32, vp, vp, i32, i32, i32, vp, i32, i32, vp],
+        "nmd_nn_prepare": [vp, i32, i32, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp, vp,
+                           vp],
+        "nmd_nn_head_loss": [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp],
+        "nmd_nn_head_infer": [vp, i32, i32, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp],
+        "nmd_nn_adam": [vp, vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float,
+                        ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, i32, i32],
+        "nmd_nn_cast_weight": [vp, vp, i32, i32, vp, vp],
+        "nmd_organ_mean_map": [vp, i32, vp, i32, vp],
+        "nmd_debug_mfma": [vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -281,6 +307,105 @@ def nmd_debug_xs(ctx, phantom_id, energies, out):
                                             _dptr(energies), _dptr(out)))
 
 
+# ---- denoiser entry points (include/nmdose_nn.h) ----------------------------
+def _src(x0, c0=None, up0=False, x1=None, c1=0):
+    """Convolution input [x0 | x1]; channel counts default to the tensors' last
+    dim.  The structure keeps references to the tensors so that their memory
+    outlives it."""
+    c0 = int(x0.shape[-1]) if c0 is None else int(c0)
+    if x1 is not None and not c1:
+        c1 = int(x1.shape[-1])
+    s = nmd_nn_src(x0.data_ptr(), c0, 1 if up0 else 0,
+                   None if x1 is None else x1.data_ptr(), int(c1))
+    s._keep = (x0, x1)
+    return s
+
+
+def _box(box):
+    return (ctypes.c_int32 * 6)(*[int(b) for b in box])
+
+
+def nmd_conv3d_fwd(ctx, dims, src: nmd_nn_src, weight, bias, c_out, relu, mask, y):
+    n, d, h, w = dims
+    _check(ctx, load_library().nmd_conv3d_fwd(ctx, n, d, h, w, ctypes.byref(src), _dptr(weight),
+                                              _dptr(bias), int(c_out), 1 if relu else 0,
+                                              _dptr(mask), _dptr(y)))
+
+
+def nmd_conv3d_bwd_data(ctx, dims, dy, c_out, weight_t, c_in, mask, dx):
+    n, d, h, w = dims
+    _check(ctx, load_library().nmd_conv3d_bwd_data(ctx, n, d, h, w, _dptr(dy), int(c_out),
+                                                   _dptr(weight_t), int(c_in), _dptr(mask),
+                                                   _dptr(dx)))
+
+
+def nmd_conv3d_bwd_weight(ctx, dims, src: nmd_nn_src, dy, c_out, dw, db=None):
+    n, d, h, w = dims
+    _check(ctx, load_library().nmd_conv3d_bwd_weight(ctx, n, d, h, w, ctypes.byref(src),
+                                                     _dptr(dy), int(c_out), _dptr(dw),
+                                                     _dptr(db)))
+
+
+def nmd_nn_pool2(ctx, dims, c, x, y):
+    n, d, h, w = dims
+    _check(ctx, load_library().nmd_nn_pool2(ctx, n, d, h, w, int(c), _dptr(x), _dptr(y)))
+
+
+def nmd_nn_combine(ctx, dims, c, mask, a, a_stride, a_off, b_mode, b, b_stride, b_off, out):
+    n, d, h, w = dims
+    _check(ctx, load_library().nmd_nn_combine(ctx, n, d, h, w, int(c), _dptr(mask), _dptr(a),
+                                              int(a_stride), int(a_off), int(b_mode), _dptr(b),
+                                              int(b_stride), int(b_off), _dptr(out)))
+
+
+def nmd_nn_prepare(ctx, shape, box, dose_lo, dose_hi, density, activity, label, x0, target,
+                   scale):
+    nz, ny, nx = shape
+    _check(ctx, load_library().nmd_nn_prepare(ctx, nz, ny, nx, _box(box), _dptr(dose_lo),
+                                              _dptr(dose_hi), _dptr(density), _dptr(activity),
+                                              _dptr(label), _dptr(x0), _dptr(target),
+                                              _dptr(scale)))
+
+
+def nmd_nn_head_loss(ctx, nvox, feat, x0, target, head_w, head_b, dfeat, grad):
+    _check(ctx, load_library().nmd_nn_head_loss(ctx, int(nvox), _dptr(feat), _dptr(x0),
+                                                _dptr(target), _dptr(head_w), _dptr(head_b),
+                                                _dptr(dfeat), _dptr(grad)))
+
+
+def nmd_nn_head_infer(ctx, shape, box, feat, x0, head_w, head_b, scale, out):
+    nz, ny, nx = shape
+    _check(ctx, load_library().nmd_nn_head_infer(ctx, nz, ny, nx, _box(box), _dptr(feat),
+                                                 _dptr(x0), _dptr(head_w), _dptr(head_b),
+                                                 _dptr(scale), _dptr(out)))
+
+
+def nmd_nn_adam(ctx, theta, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                w_bf16=None, w_t_bf16=None, c_out=0, c_in=0):
+    _check(ctx, load_library().nmd_nn_adam(ctx, _dptr(theta), _dptr(m), _dptr(v), _dptr(grad),
+                                           int(theta.numel()), int(step), float(lr),
+                                           float(beta1), float(beta2), float(eps),
+                                           _dptr(w_bf16), _dptr(w_t_bf16), int(c_out),
+                                           int(c_in)))
+
+
+def nmd_nn_cast_weight(ctx, theta, c_out, c_in, w_bf16=None, w_t_bf16=None):
+    _check(ctx, load_library().nmd_nn_cast_weight(ctx, _dptr(theta), int(c_out), int(c_in),
+                                                  _dptr(w_bf16), _dptr(w_t_bf16)))
+
+
+def nmd_organ_mean_map(ctx, phantom_id, dose_map, n_organs):
+    out = np.zeros(n_organs)
+    _check(ctx, load_library().nmd_organ_mean_map(ctx, int(phantom_id), _dptr(dose_map),
+                                                  int(n_organs),
+                                                  out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def nmd_debug_mfma(ctx, a, b, d):
+    _check(ctx, load_library().nmd_debug_mfma(ctx, _dptr(a), _dptr(b), _dptr(d)))
+
+
 # ---- convenience layer used by the tests and the benchmark ------------------
 class Engine:
     """Owns one context and the device copies of the inputs handed to it."""
@@ -293,6 +418,7 @@ class Engine:
         self.device = torch.device("cuda", device)
         self.ctx = nmd_create(device, torch.cuda.current_stream(self.device))
         self.problems = {}
+        self.inputs = {}  # device copies: density, material, label, activity
 
     def close(self):
         if self.ctx is not None:
@@ -313,10 +439,12 @@ class Engine:
         lab = t.from_numpy(np.ascontiguousarray(prob.label, dtype=np.uint8)).to(dev)
         nmd_set_phantom(self.ctx, phantom_id, rho, mat, lab, prob.n_organs, prob.materials,
                         prob.voxel_mm)
+        act = None
         if with_activity:
             act = t.from_numpy(np.ascontiguousarray(prob.activity, dtype=np.float32)).to(dev)
             nmd_set_activity(self.ctx, phantom_id, act, prob.total_activity_bq)
         self.problems[phantom_id] = prob
+        self.inputs[phantom_id] = {"density": rho, "material": mat, "label": lab, "activity": act}
 
     def run(self, phantom_id, n, seed, **kw):
         o = nmd_run_opts_default()

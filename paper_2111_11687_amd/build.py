@@ -7,9 +7,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("nmd_kernels.hip", "nmd_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("nmd_kernels.hip", "nmd_api.hip", "nmd_nn.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("nmd_internal.hpp", "nmd_device.hpp")] + [
-    os.path.join(HERE, "..", "include", "nmdose.h")]
+    os.path.join(HERE, "..", "include", f) for f in ("nmdose.h", "nmdose_nn.h")]
 LIB = os.path.join(HERE, "libnmdose.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -97,6 +97,7 @@ struct nmd_ctx {
   float l2emin = 0, inv_dl2 = 0;
   uint32_t phase_min = 32;  // tuning: NMD_PHASE_MIN
   std::map<int, Phantom> ph;
+  DevBuf nn_scratch;  // workspace of the denoiser's backward-weight partials
   bool poisoned = false;
 };
 
@@ -879,6 +880,30 @@ nmd_status nmd_get_organ_dose(nmd_ctx *c, int32_t id, int32_t n_organs, double *
   return nmd_read_organ_dose(c, id, n_organs, rate, eps3, sig_mean);
 }
 
+nmd_status nmd_organ_mean_map(nmd_ctx *c, int32_t id, const double *map, int32_t n_organs,
+                              double *out) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->has_label) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
+  if (!map || !out || n_organs < 0 || n_organs > p->n_org)
+    return fail(c, NMD_E_INVALID, "bad map, output or n_organs");
+  DevBuf acc;
+  if ((s = dev_alloc(c, acc, (p->n_org + 1) * sizeof(double)))) return s;
+  HIP_TRY(c, launch_zero_bytes(acc.p, acc.n, c->stream));
+  HIP_TRY(c, launch_map_organ_reduce(p->rec.as<uint16_t>(), p->nvox, p->n_org, map,
+                                     acc.as<double>(), c->stream));
+  std::vector<double> h(p->n_org + 1);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), acc.p, acc.n, hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c))) return s;
+  for (int o = 1; o <= n_organs; ++o) {
+    const double cnt = (double)p->organ_count[o];
+    out[o - 1] = cnt > 0 ? h[o] / cnt : 0.0;
+  }
+  return NMD_OK;
+}
+
 nmd_status nmd_get_organ_score(nmd_ctx *c, int32_t id, int32_t n_organs, double *rate) {
   nmd_status s = check_ctx(c);
   if (s) return s;
@@ -1101,3 +1126,38 @@ nmd_status nmd_debug_xs(nmd_ctx *c, int32_t id, uint64_t n, const float *energie
 }
 
 }  // extern "C"
+
+// ---- services of the context for the denoiser entry points ------------------
+namespace nmd {
+
+nmd_status ctx_enter(nmd_ctx *c) { return check_ctx(c); }
+
+nmd_status ctx_fail(nmd_ctx *c, nmd_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return fail(c, s, "%s", buf);
+}
+
+nmd_status ctx_hip(nmd_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return NMD_OK;
+  return fail(c, e == hipErrorOutOfMemory ? NMD_E_OOM : NMD_E_HIP, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+hipStream_t ctx_stream(const nmd_ctx *c) { return c->stream; }
+
+nmd_status ctx_scratch(nmd_ctx *c, size_t bytes, void **p) {
+  if (c->nn_scratch.n < bytes) {
+    // the old buffer may still be read by queued work: drain first
+    nmd_status s = sync(c);
+    if (s) return s;
+    if ((s = dev_alloc(c, c->nn_scratch, bytes))) return s;
+  }
+  *p = c->nn_scratch.p;
+  return NMD_OK;
+}
+
+}  // namespace nmd

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/nmdose.h"
+
 namespace nmd {
 
 constexpr int kMaxPhantoms = 64;
@@ -121,5 +123,17 @@ hipError_t launch_zero_bytes(void *p, uint64_t nbytes, hipStream_t s);
 hipError_t launch_advance(const PhantomDesc *desc, const RunIds &ids, unsigned long long n,
                           hipStream_t s);
 hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
+hipError_t launch_map_organ_reduce(const uint16_t *rec, uint64_t nvox, int n_org,
+                                   const double *map, double *acc /* [n_org+1] */,
+                                   hipStream_t s);
+
+// Services of the context used by the denoiser entry points (nmd_nn.hip).
+nmd_status ctx_enter(nmd_ctx *c);  // validates the context and makes its device current
+nmd_status ctx_fail(nmd_ctx *c, nmd_status s, const char *fmt, ...);
+nmd_status ctx_hip(nmd_ctx *c, hipError_t e, const char *what);  // NMD_OK on hipSuccess
+hipStream_t ctx_stream(const nmd_ctx *c);
+// A context-owned device workspace of at least `bytes`, reused across calls
+// (stream-ordered: only work on the context stream may use it).
+nmd_status ctx_scratch(nmd_ctx *c, size_t bytes, void **p);
 
 }  // namespace nmd

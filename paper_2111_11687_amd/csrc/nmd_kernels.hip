@@ -734,6 +734,53 @@ hipError_t launch_organ_reduce(const uint16_t *rec, const float4 *palette,
   return hipGetLastError();
 }
 
+// Organ sums of a caller-supplied map (for example a denoised dose-rate map),
+// with the same wave-level segmentation by label.
+__global__ __launch_bounds__(256) void map_organ_kernel(const uint16_t *__restrict__ rec,
+                                                        uint64_t nvox, int n_org,
+                                                        const double *__restrict__ map,
+                                                        double *__restrict__ out) {
+  __shared__ double s_acc[kMaxOrganSlots];
+  for (int i = threadIdx.x; i < kMaxOrganSlots; i += 256) s_acc[i] = 0.0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t nround = (nvox + stride - 1) / stride;
+  uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = lane_id();
+  for (uint64_t it = 0; it < nround; ++it, v += stride) {
+    uint32_t o = 0;
+    double a = 0.0;
+    if (v < nvox) {
+      o = (uint32_t)rec[v] >> 8;
+      if (o != 0 && (int)o <= n_org) a = map[v];
+    }
+    bool pending = o != 0 && (int)o <= n_org;
+    for (;;) {
+      const unsigned long long m = __ballot(pending);
+      if (m == 0) break;
+      const int lead = __ffsll((long long)m) - 1;
+      const uint32_t lo = __shfl(o, lead, 64);
+      const bool mine = pending && o == lo;
+      const double sa = wave_sum(mine ? a : 0.0);
+      if ((int)lane == lead) atomicAdd(&s_acc[lo], sa);
+      pending = pending && !mine;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= n_org; i += 256)
+    if (s_acc[i] != 0.0) atomicAdd(&out[i], s_acc[i]);
+}
+
+hipError_t launch_map_organ_reduce(const uint16_t *rec, uint64_t nvox, int n_org,
+                                   const double *map, double *acc, hipStream_t s) {
+  uint64_t blocks = (nvox + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(map_organ_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, rec, nvox,
+                     n_org, map, acc);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Test hooks
 // ---------------------------------------------------------------------------
