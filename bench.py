@@ -38,6 +38,10 @@ VALU_PER_HISTORY = 60         # alias sample, voxel coordinates, photon starts
 VALU_PER_MERGED = 20          # tally and organ flush per distinct voxel
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: one lane-operation per lane per cycle
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# Bytes moved beyond L2 per decay by the transport kernel on the patient
+# phantom: FETCH_SIZE x 2 + WRITE_SIZE of rocprofv3 --pmc runs, scaled
+# against a profiled 256 MiB copy (profiles/transport_patient256x256x320_counters.md).
+TRANSPORT_TRAFFIC_BYTES_PER_DECAY = 2806.0
 
 
 def valu_ops(stats):
@@ -79,11 +83,18 @@ def main():
     ap.add_argument("--decays-per-step", type=int, default=10 ** 8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("patient", "batch64", "denoiser"), default="patient",
+    ap.add_argument("--workload", choices=("patient", "batch64", "denoiser", "organ-time"),
+                    default="patient",
                     help="patient: the 256x256x320 phantom (the headline metric); batch64: 64 "
                          "uneven phantoms, 10^7 decays each per step, one graph-captured "
                          "launch per step with the autotuned chunk; denoiser: U-Net training "
-                         "steps on 128x128x160 boxes and inference on the whole phantom")
+                         "steps on 128x128x160 boxes and inference on the whole phantom; "
+                         "organ-time: time to <=1%% organ dose, plain MC vs MC + trained "
+                         "denoiser with the MC judge and fallback, on held-out patients")
+    ap.add_argument("--phantoms", type=int, default=2,
+                    help="organ-time: held-out patients (seeds 20008 onward)")
+    ap.add_argument("--weights", default=None,
+                    help="organ-time: trained denoiser (.npz); default: the packaged one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first copy BYTES with a plain device copy, to scale the "
                          "HBM byte counters of a profile against a known size")
@@ -107,6 +118,8 @@ def main():
         return bench_batch(args)
     if args.workload == "denoiser":
         return bench_denoiser(args)
+    if args.workload == "organ-time":
+        return bench_organ_time(args)
     prob = P.patient_phantom()
     eng = B.Engine(0)
     eng.set_problem(0, prob)
@@ -169,7 +182,9 @@ def main():
                    "decays_per_step": nd, "decays_per_job": total,
                    "tally": "f64", "transport": "f32"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": TRANSPORT_TRAFFIC_BYTES_PER_DECAY * nd,
+                     "traffic_unit": "bytes beyond L2 per launch (profiled)",
                      "kernel": "transport_kernel", "kernel_ms": kern_ms,
                      "ops_per_decay": ops_launch / nd},
     }
@@ -342,6 +357,69 @@ def bench_denoiser(args):
         res["cpu_baseline"] = cpu_baseline_denoiser(min(args.cpu_seconds, 15.0))
     eng.close()
     print(json.dumps(res), flush=True)
+
+
+WEIGHTS = os.path.join(ROOT, "paper_2111_11687_amd", "weights", "unet16_patient.npz")
+
+
+def bench_organ_time(args):
+    """Time to <= 1% organ dose on held-out patients (256x256x320):
+    plain Monte Carlo until 2 sigma <= 1% for every organ, against 10^7
+    decays + the trained denoiser + the Monte Carlo judge and fallback.  Both
+    results are compared with an untimed 10^9-decay reference."""
+    import torch
+    from paper_2111_11687_amd import binding as B
+    from paper_2111_11687_amd import denoiser as DN
+    from paper_2111_11687_amd import phantoms as P
+    from paper_2111_11687_amd import train_denoiser as T
+
+    eng = B.Engine(0)
+    net = DN.UNet(eng)
+    bias = net.load(args.weights or WEIGHTS)
+    tol = 0.01
+    rows = []
+    ws = None
+    for k in range(args.phantoms):
+        seed = 20008 + k
+        prob = P.patient_phantom(seed=seed)
+        if ws is None:
+            ws = DN.Workspace(eng, prob.shape, train=False)
+        # warm-up of both paths on this phantom (allocations, first launches)
+        T.organ_dose_with_fallback(eng, net, prob, 2 * 10 ** 6, 5, bias, tol=1.0, ws=ws)
+        mc_org, mc_sig, mc_n, mc_s, mc_ok = T.plain_mc_to_tolerance(
+            eng, prob, 10 ** 7, seed + 3 * 10 ** 6, tol=tol, max_decays=2 * 10 ** 10)
+        dn = T.organ_dose_with_fallback(eng, net, prob, 10 ** 7, seed + 4 * 10 ** 6, bias,
+                                        tol=tol, ws=ws, max_decays=2 * 10 ** 10)
+        eng.set_problem(T.PID_A, prob)
+        eng.run(T.PID_A, 10 ** 9, seed + 2 * 10 ** 6)
+        ref, _, ref_sig = eng.organs(T.PID_A)
+        present = ref > 0  # organs with at least one voxel in this phantom
+        e_mc = np.abs(mc_org - ref)[present] / ref[present]
+        e_dn = np.abs(dn["organ"] - ref)[present] / ref[present]
+        row = {"seed": seed, "mc_s": mc_s, "mc_decays": mc_n, "mc_reached": mc_ok,
+               "dn_s": dn["seconds"], "dn_decays": dn["decays"], "dn_reached": dn["reached"],
+               "dn_stage_s": dn["seconds_denoiser_stage"],
+               "organs_from_denoiser": int(sum(1 for x in dn["source"] if x == "denoiser")),
+               "mc_max_err": float(e_mc.max()), "dn_max_err": float(e_dn.max()),
+               "ref_max_sigma": float(ref_sig[present].max()),
+               "organs_present": int(present.sum())}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    t_mc = float(np.mean([r["mc_s"] for r in rows]))
+    t_dn = float(np.mean([r["dn_s"] for r in rows]))
+    out = {
+        "metric": "time to <=1% organ dose: MC vs MC+denoiser",
+        "value": t_mc / t_dn, "unit": "x (plain MC time / MC+denoiser time)",
+        "n_gpus": 1, "steps": len(rows), "warmup": 1, "ms_per_step": t_dn * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "held-out patient phantoms 256x256x320 (seeds 20008+), 27 "
+                               "organs; plain MC until 2 sigma <= 1% for every organ vs 10^7 "
+                               "decays + U-Net denoiser + MC judge and fallback",
+                   "mc_seconds": t_mc, "mc_denoiser_seconds": t_dn, "phantoms": rows},
+    }
+    eng.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -111,16 +111,20 @@ nmd_status nmd_nn_prepare(nmd_ctx *ctx, int32_t nz, int32_t ny, int32_t nx, cons
 
 /* Head, loss and the head's backward for one batch of nvox voxels:
  *   pred[v] = x0[v][0] + sum_i head_w[i] feat[v][i] + head_b[0]   (FP32)
- *   loss    = sum_v (pred[v] - target[v])^2
- *   g[v]    = 2 (pred[v] - target[v]) / nvox
+ *   w[v]    = 1 / max(target[v], weight_floor) if weight_floor > 0, else 1
+ *   loss    = sum_v w[v] (pred[v] - target[v])^2
+ *   g[v]    = 2 w[v] (pred[v] - target[v]) / nvox
  *   dfeat[v][i] = [feat[v][i] > 0] * bf16(g[v] head_w[i])
  *   grad[0..15] = sum_v g[v] feat[v][i],  grad[16] = sum_v g[v],
  *   grad[17] = loss.
- * feat has 16 channels, x0 8; head_w FP32[16], head_b FP32[1]; grad is a
- * device float[18]. */
+ * The weight is the inverse of the target, a variance proxy: Monte Carlo
+ * dose noise has a variance roughly proportional to the dose.  feat has 16
+ * channels, x0 8; head_w FP32[16], head_b FP32[1]; grad is a device
+ * float[18]. */
 nmd_status nmd_nn_head_loss(nmd_ctx *ctx, int64_t nvox, const uint16_t *feat,
                             const uint16_t *x0, const float *target, const float *head_w,
-                            const float *head_b, uint16_t *dfeat, float *grad);
+                            const float *head_b, float weight_floor, uint16_t *dfeat,
+                            float *grad);
 
 /* Head at inference: for every voxel v of the box (box as nmd_nn_prepare),
  * out[full-map voxel] = max(pred[v], 0) * scale[0] (FP64); voxels of out

@@ -157,14 +157,19 @@ def forward(params, x0: torch.Tensor, bf16_storage: bool = True, keep=None):
     return pred
 
 
-def mse(pred: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
-    return ((pred - target.to(F64)) ** 2).mean()
+def mse(pred: torch.Tensor, target: torch.Tensor, weight_floor: float = 0.0) -> torch.Tensor:
+    """Mean of w (pred - target)^2 with w = 1/max(target, weight_floor) when
+    weight_floor > 0 (inverse-variance weighting for noise whose variance
+    grows with the dose), else w = 1."""
+    t = target.to(F64)
+    w = 1.0 / torch.clamp(t, min=weight_floor) if weight_floor > 0 else torch.ones_like(t)
+    return (w * (pred - t) ** 2).mean()
 
 
-def loss_and_grads(params, x0, target, bf16_storage: bool = True):
+def loss_and_grads(params, x0, target, bf16_storage: bool = True, weight_floor: float = 0.0):
     """Loss and d(loss)/d(param) for every parameter (FP64)."""
     leaves = {k: v.detach().to(F64).clone().requires_grad_(True) for k, v in params.items()}
-    loss = mse(forward(leaves, x0, bf16_storage), target)
+    loss = mse(forward(leaves, x0, bf16_storage), target, weight_floor)
     loss.backward()
     return loss.item(), {k: v.grad for k, v in leaves.items()}
 

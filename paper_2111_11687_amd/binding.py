@@ -112,7 +112,7 @@ def load_library(path: str = LIB_PATH):
         "nmd_nn_combine": [vp, i32, i32, i32, i32, i32, vp, vp, i32, i32, i32, vp, i32, i32, vp],
         "nmd_nn_prepare": [vp, i32, i32, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp, vp,
                            vp],
-        "nmd_nn_head_loss": [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp],
+        "nmd_nn_head_loss": [vp, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_float, vp, vp],
         "nmd_nn_head_infer": [vp, i32, i32, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp],
         "nmd_nn_adam": [vp, vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float,
                         ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, i32, i32],
@@ -367,10 +367,11 @@ def nmd_nn_prepare(ctx, shape, box, dose_lo, dose_hi, density, activity, label, 
                                               _dptr(scale)))
 
 
-def nmd_nn_head_loss(ctx, nvox, feat, x0, target, head_w, head_b, dfeat, grad):
+def nmd_nn_head_loss(ctx, nvox, feat, x0, target, head_w, head_b, dfeat, grad,
+                     weight_floor=0.0):
     _check(ctx, load_library().nmd_nn_head_loss(ctx, int(nvox), _dptr(feat), _dptr(x0),
                                                 _dptr(target), _dptr(head_w), _dptr(head_b),
-                                                _dptr(dfeat), _dptr(grad)))
+                                                float(weight_floor), _dptr(dfeat), _dptr(grad)))
 
 
 def nmd_nn_head_infer(ctx, shape, box, feat, x0, head_w, head_b, scale, out):

@@ -228,11 +228,25 @@ struct WgradArgs {
   int32_t n_vg, ncg;                           // voxel groups; column groups per chunk
 };
 
+// Element pair j of two packed bf16 vectors as one dword: (lo[j], hi[j]).
+__device__ __forceinline__ uint32_t pair_of(const u32x4_t &lo, const u32x4_t &hi, int j) {
+  const uint32_t wl = (j >> 1) == 0 ? lo.x : (j >> 1) == 1 ? lo.y : (j >> 1) == 2 ? lo.z : lo.w;
+  const uint32_t wh = (j >> 1) == 0 ? hi.x : (j >> 1) == 1 ? hi.y : (j >> 1) == 2 ? hi.z : hi.w;
+  return (j & 1) ? ((wl >> 16) | (wh & 0xffff0000u)) : ((wl & 0xffffu) | (wh << 16));
+}
+
 template <int CC, int NCBO, int NBW>
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   constexpr int NB = (27 * CC + 15) / 16;  // column blocks per chunk
   constexpr int NC8 = CC / 8;
   constexpr int COUT = NCBO * 16;
+  // staging items: two x-neighbouring voxels x 8 channels, voxel pairs fastest
+  constexpr int XPAIRS = WHV / 2;                     // 216 (halo rows are 18 voxels)
+  constexpr int NXI = XPAIRS * NC8;
+  constexpr int NXL = (NXI + 255) / 256;
+  constexpr int DPAIRS = WTX * WTY * WTZ / 2;         // 64
+  constexpr int NDI = DPAIRS * (COUT / 8);
+  constexpr int NDL = (NDI + 255) / 256;
   __shared__ __align__(16) uint16_t s_x[CC * WCP];
   __shared__ __align__(16) uint16_t s_dp[COUT * WDP];
 
@@ -242,6 +256,14 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   const int lx = lane & 15, g = lane >> 4;
   const int cbase = chunk * CC;
   const int tpv = a.tiles_x * a.tiles_y * a.tiles_z;
+
+  const bool first = cbase < a.src.c0;
+  const uint16_t *xbase = first ? a.src.x0 : a.src.x1;
+  const int xcs = first ? a.src.c0 : a.src.c1;
+  const int xcoff = first ? cbase : cbase - a.src.c0;
+  const bool up = first && a.src.up0;
+  const int Ds = up ? (a.d + 1) >> 1 : a.d, Hs = up ? (a.h + 1) >> 1 : a.h,
+            Ws = up ? (a.w_ + 1) >> 1 : a.w_;
 
   f32x4_t acc[NCBO][NBW];
 #pragma unroll
@@ -264,56 +286,94 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
     colsh[j] = tp % 3;
   }
 
-  for (int t = vg; t < a.n_tiles; t += a.n_vg) {
+  // registers holding the next tile while the current one is computed
+  u32x4_t px[NXL][2], pd[NDL][2];
+  auto load = [&](int t) {
     const int nb = t / tpv, tl = t - nb * tpv;
     const int tx = tl % a.tiles_x, r0 = tl / a.tiles_x, ty = r0 % a.tiles_y, tz = r0 / a.tiles_y;
     const int x0 = tx * WTX, y0 = ty * WTY, z0 = tz * WTZ;
-    __syncthreads();
-    // dy tile, transposed to channel-major
-    for (int u = threadIdx.x; u < WTX * WTY * WTZ * (COUT / 8); u += 256) {
-      const int tv = u / (COUT / 8), c8 = u - tv * (COUT / 8);
-      const int xx = tv % WTX, yy = (tv / WTX) % WTY, zz = tv / (WTX * WTY);
-      const int x = x0 + xx, y = y0 + yy, z = z0 + zz;
-      u32x4_t val = {0u, 0u, 0u, 0u};
-      if (x < a.w_ && y < a.h && z < a.d)
-        val = *reinterpret_cast<const u32x4_t *>(
-            a.dy + ((((size_t)nb * a.d + z) * a.h + y) * a.w_ + x) * COUT + c8 * 8);
-      const uint32_t wv[4] = {val.x, val.y, val.z, val.w};
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        s_dp[(c8 * 8 + j) * WDP + tv] = (uint16_t)((j & 1) ? wv[j >> 1] >> 16 : wv[j >> 1]);
-    }
-    // input halo of this chunk, transposed to channel-major
-    {
-      const bool first = cbase < a.src.c0;
-      const uint16_t *base = first ? a.src.x0 : a.src.x1;
-      const int cs = first ? a.src.c0 : a.src.c1;
-      const int coff = first ? cbase : cbase - a.src.c0;
-      const bool up = first && a.src.up0;
-      const int Ds = up ? (a.d + 1) >> 1 : a.d, Hs = up ? (a.h + 1) >> 1 : a.h,
-                Ws = up ? (a.w_ + 1) >> 1 : a.w_;
-      for (int u = threadIdx.x; u < WHV * NC8; u += 256) {
-        const int hv = u / NC8, c8 = u - hv * NC8;
-        const int hx = hv % WHX, hy = (hv / WHX) % WHY, hz = hv / (WHX * WHY);
-        int z = z0 - 1 + hz, y = y0 - 1 + hy, x = x0 - 1 + hx;
-        u32x4_t val = {0u, 0u, 0u, 0u};
-        if (z >= 0 && z < a.d && y >= 0 && y < a.h && x >= 0 && x < a.w_) {
+    for (int i = 0; i < NXL; ++i) {
+      const int u = threadIdx.x + 256 * i;
+      px[i][0] = px[i][1] = u32x4_t{0u, 0u, 0u, 0u};
+      if (u < NXI) {
+        const int c8 = u / XPAIRS, pr = u - c8 * XPAIRS;
+        const int hx = 2 * (pr % (WHX / 2)), hy = (pr / (WHX / 2)) % WHY,
+                  hz = pr / ((WHX / 2) * WHY);
+        int z = z0 - 1 + hz, y = y0 - 1 + hy;
+        if (z >= 0 && z < a.d && y >= 0 && y < a.h) {
           if (up) {
             z >>= 1;
             y >>= 1;
-            x >>= 1;
           }
-          const size_t vox = (((size_t)nb * Ds + z) * Hs + y) * Ws + x;
-          val = *reinterpret_cast<const u32x4_t *>(base + vox * cs + coff + c8 * 8);
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            int x = x0 - 1 + hx + e;
+            if (x >= 0 && x < a.w_) {
+              if (up) x >>= 1;
+              const size_t vox = (((size_t)nb * Ds + z) * Hs + y) * Ws + x;
+              px[i][e] = *reinterpret_cast<const u32x4_t *>(xbase + vox * xcs + xcoff + c8 * 8);
+            }
+          }
         }
-        const uint32_t wv[4] = {val.x, val.y, val.z, val.w};
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NDL; ++i) {
+      const int u = threadIdx.x + 256 * i;
+      pd[i][0] = pd[i][1] = u32x4_t{0u, 0u, 0u, 0u};
+      if (u < NDI) {
+        const int c8 = u / DPAIRS, pr = u - c8 * DPAIRS;
+        const int xx = 2 * (pr % (WTX / 2)), yy = (pr / (WTX / 2)) % WTY, zz = pr / ((WTX / 2) * WTY);
+        const int y = y0 + yy, z = z0 + zz;
+        if (y < a.h && z < a.d) {
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int x = x0 + xx + e;
+            if (x < a.w_)
+              pd[i][e] = *reinterpret_cast<const u32x4_t *>(
+                  a.dy + ((((size_t)nb * a.d + z) * a.h + y) * a.w_ + x) * COUT + c8 * 8);
+          }
+        }
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < NXL; ++i) {
+      const int u = threadIdx.x + 256 * i;
+      if (u < NXI) {
+        const int c8 = u / XPAIRS, pr = u - c8 * XPAIRS;
+        const int hx = 2 * (pr % (WHX / 2)), hy = (pr / (WHX / 2)) % WHY,
+                  hz = pr / ((WHX / 2) * WHY);
         const int o = (hz * WHY + hy) * WXP + hx;
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          s_x[(c8 * 8 + j) * WCP + o] = (uint16_t)((j & 1) ? wv[j >> 1] >> 16 : wv[j >> 1]);
+          *reinterpret_cast<uint32_t *>(s_x + (c8 * 8 + j) * WCP + o) = pair_of(px[i][0], px[i][1], j);
       }
     }
+#pragma unroll
+    for (int i = 0; i < NDL; ++i) {
+      const int u = threadIdx.x + 256 * i;
+      if (u < NDI) {
+        const int c8 = u / DPAIRS, pr = u - c8 * DPAIRS;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          *reinterpret_cast<uint32_t *>(s_dp + (c8 * 8 + j) * WDP + 2 * pr) =
+              pair_of(pd[i][0], pd[i][1], j);
+      }
+    }
+  };
+
+  // a contiguous run of tiles (x fastest): neighbouring halos meet in L2
+  const int t_begin = (int)(((int64_t)a.n_tiles * vg) / a.n_vg);
+  const int t_end = (int)(((int64_t)a.n_tiles * (vg + 1)) / a.n_vg);
+  if (t_begin < t_end) load(t_begin);
+  for (int t = t_begin; t < t_end; ++t) {
+    __syncthreads();  // the previous tile's reads of LDS are done
+    store();
     __syncthreads();
+    if (t + 1 < t_end) load(t + 1);  // in flight during the MFMAs
     // 4 K steps of 32 voxels; group g takes 8 voxels of tile row 2s + g/2
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -330,14 +390,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
         const u32x4_t lo = *reinterpret_cast<const u32x4_t *>(pb);
         const uint32_t hi = *reinterpret_cast<const uint32_t *>(pb + 8);
         const uint32_t d[5] = {lo.x, lo.y, lo.z, lo.w, hi};
-        u32x4_t bv;
         uint32_t o4[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const uint32_t s1 = (d[k] >> 16) | (d[k + 1] << 16);
           o4[k] = colsh[j] == 0 ? d[k] : (colsh[j] == 1 ? s1 : d[k + 1]);
         }
-        bv = u32x4_t{o4[0], o4[1], o4[2], o4[3]};
+        u32x4_t bv = u32x4_t{o4[0], o4[1], o4[2], o4[3]};
         if (!colok[j]) bv = u32x4_t{0u, 0u, 0u, 0u};
 #pragma unroll
         for (int i = 0; i < NCBO; ++i) acc[i][j] = mfma_bf16(av[i], bv, acc[i][j]);
@@ -362,15 +421,26 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   }
 }
 
-// Sum of n_part partial vectors of length n (fixed order).
+// out[e] = sum over p of part[p*n + e].  A block takes 64 consecutive
+// elements; its 4 waves each sum every 4th partial in order (one coalesced
+// 256-byte row per load), then the 4 wave sums are added in a fixed order:
+// the result does not depend on the launch.
 __global__ __launch_bounds__(256) void sum_parts_kernel(const float *__restrict__ part,
                                                         int64_t n, int n_part,
                                                         float *__restrict__ out) {
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * 256) {
-    float s = 0.f;
-    for (int p = 0; p < n_part; ++p) s += part[(size_t)p * n + e];
-    out[e] = s;
+  __shared__ float s[4][64];
+  const int el = threadIdx.x & 63, ln = threadIdx.x >> 6;
+  for (int64_t e0 = (int64_t)blockIdx.x * 64; e0 < n; e0 += (int64_t)gridDim.x * 64) {
+    const int64_t e = e0 + el;
+    float acc = 0.f;
+    if (e < n) {
+#pragma unroll 8
+      for (int p = ln; p < n_part; p += 4) acc += part[(size_t)p * n + e];
+    }
+    s[ln][el] = acc;
+    __syncthreads();
+    if (ln == 0 && e < n) out[e] = (s[0][el] + s[1][el]) + (s[2][el] + s[3][el]);
+    __syncthreads();
   }
 }
 
@@ -527,18 +597,26 @@ __global__ __launch_bounds__(256) void body_stats_kernel(int ny, int nx, Box bx,
   if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = s[threadIdx.x][0];
 }
 
-__global__ void body_scale_kernel(const double *__restrict__ part, int n_part,
-                                  double *__restrict__ scale) {
-  if (threadIdx.x != 0) return;
-  double sd = 0.0, sa = 0.0, sc = 0.0;
-  for (int p = 0; p < n_part; ++p) {
-    sd += part[3 * p];
-    sa += part[3 * p + 1];
-    sc += part[3 * p + 2];
+__global__ __launch_bounds__(256) void body_scale_kernel(const double *__restrict__ part,
+                                                         int n_part,
+                                                         double *__restrict__ scale) {
+  __shared__ double s[3][256];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int p = threadIdx.x; p < n_part; p += 256)
+    for (int q = 0; q < 3; ++q) a[q] += part[3 * p + q];
+  for (int q = 0; q < 3; ++q) s[q][threadIdx.x] = a[q];
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k)
+      for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + k];
+    __syncthreads();
   }
-  const double md = sc > 0 ? sd / sc : 0.0, ma = sc > 0 ? sa / sc : 0.0;
-  scale[0] = md > 0 ? md : 1.0;
-  scale[1] = ma > 0 ? ma : 1.0;
+  if (threadIdx.x == 0) {
+    const double sd = s[0][0], sa = s[1][0], sc = s[2][0];
+    const double md = sc > 0 ? sd / sc : 0.0, ma = sc > 0 ? sa / sc : 0.0;
+    scale[0] = md > 0 ? md : 1.0;
+    scale[1] = ma > 0 ? ma : 1.0;
+  }
 }
 
 __global__ __launch_bounds__(256) void prepare_kernel(int ny, int nx, Box bx,
@@ -571,6 +649,7 @@ __global__ __launch_bounds__(256) void head_loss_kernel(uint64_t nvox,
                                                         const float *__restrict__ tgt,
                                                         const float *__restrict__ hw,
                                                         const float *__restrict__ hb,
+                                                        float wfloor,
                                                         uint16_t *__restrict__ dfeat,
                                                         float *__restrict__ part) {
   __shared__ float s[18][256];
@@ -596,8 +675,10 @@ __global__ __launch_bounds__(256) void head_loss_kernel(uint64_t nvox,
 #pragma unroll
     for (int i = 0; i < 16; ++i) hsum = fmaf(w[i], f[i], hsum);
     const float pred = bf2f(x0[v * 8]) + (hsum + b);
-    const float e = pred - tgt[v];
-    const float gv = gscale * e;
+    const float t = tgt[v];
+    const float e = pred - t;
+    const float wv = wfloor > 0.f ? 1.0f / fmaxf(t, wfloor) : 1.0f;
+    const float gv = gscale * (wv * e);
     float gf[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -605,7 +686,7 @@ __global__ __launch_bounds__(256) void head_loss_kernel(uint64_t nvox,
       acc[i] = fmaf(gv, f[i], acc[i]);
     }
     acc[16] += gv;
-    acc[17] = fmaf(e, e, acc[17]);
+    acc[17] = fmaf(wv * e, e, acc[17]);
     const u32x4_t o0 = {pack2(gf[0], gf[1]), pack2(gf[2], gf[3]), pack2(gf[4], gf[5]),
                         pack2(gf[6], gf[7])};
     const u32x4_t o1 = {pack2(gf[8], gf[9]), pack2(gf[10], gf[11]), pack2(gf[12], gf[13]),
@@ -894,8 +975,8 @@ nmd_status nmd_conv3d_bwd_weight(nmd_ctx *c, int32_t n, int32_t d, int32_t h, in
   else if (ncbo == 2) hipLaunchKernelGGL((wgrad_kernel<32, 2, 14>), grid, dim3(256), 0, st, a);
   else hipLaunchKernelGGL((wgrad_kernel<32, 4, 7>), grid, dim3(256), 0, st, a);
   if ((s = ctx_hip(c, hipGetLastError(), "wgrad_kernel"))) return s;
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(grid_for((uint64_t)ne, 2048)), dim3(256), 0, st,
-                     a.part, ne, (int)nvg, dw);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)std::min<int64_t>((ne + 63) / 64, 4096)),
+                     dim3(256), 0, st, a.part, ne, (int)nvg, dw);
   if ((s = ctx_hip(c, hipGetLastError(), "sum_parts_kernel"))) return s;
   if (db) {
     hipLaunchKernelGGL(chan_sum_kernel, dim3(bgrid), dim3(256), 0, st, dy, nvox, c_out, bpart);
@@ -972,7 +1053,7 @@ nmd_status nmd_nn_prepare(nmd_ctx *c, int32_t nz, int32_t ny, int32_t nx, const 
   hipLaunchKernelGGL(body_stats_kernel, dim3(nb), dim3(256), 0, st, ny, nx, bx, dose_lo,
                      activity, label, part);
   if ((s = ctx_hip(c, hipGetLastError(), "body_stats_kernel"))) return s;
-  hipLaunchKernelGGL(body_scale_kernel, dim3(1), dim3(64), 0, st, part, (int)nb, scale);
+  hipLaunchKernelGGL(body_scale_kernel, dim3(1), dim3(256), 0, st, part, (int)nb, scale);
   if ((s = ctx_hip(c, hipGetLastError(), "body_scale_kernel"))) return s;
   hipLaunchKernelGGL(prepare_kernel, dim3(grid_for(work)), dim3(256), 0, st, ny, nx, bx, dose_lo,
                      dose_hi, density, activity, scale, x0, target);
@@ -981,7 +1062,7 @@ nmd_status nmd_nn_prepare(nmd_ctx *c, int32_t nz, int32_t ny, int32_t nx, const 
 
 nmd_status nmd_nn_head_loss(nmd_ctx *c, int64_t nvox, const uint16_t *feat, const uint16_t *x0,
                             const float *target, const float *head_w, const float *head_b,
-                            uint16_t *dfeat, float *grad) {
+                            float weight_floor, uint16_t *dfeat, float *grad) {
   nmd_status s = ctx_enter(c);
   if (s) return s;
   if (nvox < 1 || nvox >= (1ll << 31) || !feat || !x0 || !target || !head_w || !head_b ||
@@ -992,8 +1073,9 @@ nmd_status nmd_nn_head_loss(nmd_ctx *c, int64_t nvox, const uint16_t *feat, cons
   if ((s = ctx_scratch(c, (size_t)nb * 18 * sizeof(float), &ws))) return s;
   float *part = static_cast<float *>(ws);
   hipStream_t st = ctx_stream(c);
+  if (!(weight_floor >= 0.f)) return ctx_fail(c, NMD_E_INVALID, "weight_floor must be >= 0");
   hipLaunchKernelGGL(head_loss_kernel, dim3(nb), dim3(256), 0, st, (uint64_t)nvox, feat, x0,
-                     target, head_w, head_b, dfeat, part);
+                     target, head_w, head_b, weight_floor, dfeat, part);
   if ((s = ctx_hip(c, hipGetLastError(), "head_loss_kernel"))) return s;
   hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, part, (int64_t)18, (int)nb,
                      grad);

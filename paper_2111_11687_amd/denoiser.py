@@ -127,14 +127,21 @@ class UNet:
             dst.copy_(val.reshape(dst.shape).to(dst.device))
         self.refresh()
 
-    def save(self, path):
-        st = self.state()
-        np.savez(path, step=self.step, **{k: v.numpy() for k, v in st.items()})
+    def save(self, path, bias=None):
+        """Parameters (and, if given, the per-organ bias table of the
+        fallback) as an uncompressed .npz of plain arrays."""
+        st = {k: v.numpy() for k, v in self.state().items()}
+        if bias is not None:
+            st["organ_bias"] = np.asarray(bias, dtype=np.float64)
+        np.savez(path, step=self.step, **st)
 
     def load(self, path):
+        """Loads parameters saved by save(); returns the organ bias table or
+        None."""
         with np.load(path, allow_pickle=False) as z:
-            self.load_state({k: z[k] for k in z.files if k != "step"})
+            self.load_state({k: z[k] for k in z.files if k not in ("step", "organ_bias")})
             self.step = int(z["step"])
+            return np.array(z["organ_bias"]) if "organ_bias" in z.files else None
 
     # ------------------------------------------------------------------ run
     def forward(self, ws, events=None):
@@ -207,12 +214,13 @@ class UNet:
         dgrad("enc0b", L0, g["e0b"], a["e0a"], g["e0a"])
         wgrad("enc0a", L0, B._src(ws.x0), g["e0a"])
 
-    def loss_and_grad(self, ws, events=None):
+    def loss_and_grad(self, ws, events=None, weight_floor=0.0):
         """Forward, loss and backward; the loss stays on the device
-        (ws.loss_value(), which synchronises, reads it)."""
+        (ws.loss_value(), which synchronises, reads it).  weight_floor > 0
+        weights each voxel's squared error by 1/max(target, weight_floor)."""
         self.forward(ws, events)
         B.nmd_nn_head_loss(self.ctx, ws.nvox, ws.a["d0b"], ws.x0, ws.target, self.p["head.w"],
-                           self.p["head.b"], ws.g["d0b"], self.hgrad)
+                           self.p["head.b"], ws.g["d0b"], self.hgrad, weight_floor)
         self.backward(ws)
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -228,8 +236,8 @@ class UNet:
         B.nmd_nn_adam(c, p["head.b"], p["head.b.m"], p["head.b.v"], self.hgrad[16:17], k, lr,
                       beta1, beta2, eps)
 
-    def train_step(self, ws, lr=1e-3, events=None):
-        self.loss_and_grad(ws, events)
+    def train_step(self, ws, lr=1e-3, events=None, weight_floor=0.0):
+        self.loss_and_grad(ws, events, weight_floor)
         self.adam(lr)
 
     def predict(self, ws, out, events=None):

@@ -47,53 +47,70 @@ def _run_map(eng, pid, n, seed):
     return rate
 
 
-def pick_box(label, box_shape, rng):
-    """A box of box_shape (d, h, w) centred at a random body voxel's
-    neighbourhood, clamped inside the volume."""
+def pick_box(label, box_shape, rng, organ_fraction=0.0, n_organs=None):
+    """A box of box_shape (d, h, w) clamped inside the volume.  With
+    probability organ_fraction it is centred on a random voxel of a random
+    organ (labels 1 .. n_organs - 1, the last label being the body
+    remainder), else on a random point of the body's bounding box."""
     shape = label.shape
     if any(b > s for b, s in zip(box_shape, shape)):
         raise ValueError("box larger than the phantom")
-    body = np.argwhere(label > 0)
-    lo, hi = body.min(0), body.max(0)
-    out = []
-    for a in range(3):
-        c = rng.integers(lo[a], hi[a] + 1)
-        z0 = int(np.clip(c - box_shape[a] // 2, 0, shape[a] - box_shape[a]))
-        out.append(z0)
+    centre = None
+    if organ_fraction > 0 and n_organs and rng.random() < organ_fraction:
+        o = int(rng.integers(1, n_organs))
+        vox = np.argwhere(label == o)
+        if len(vox):
+            centre = vox[int(rng.integers(len(vox)))]
+    if centre is None:
+        body = np.argwhere(label > 0)
+        lo, hi = body.min(0), body.max(0)
+        centre = [rng.integers(lo[a], hi[a] + 1) for a in range(3)]
+    out = [int(np.clip(centre[a] - box_shape[a] // 2, 0, shape[a] - box_shape[a]))
+           for a in range(3)]
     return tuple(out) + tuple(box_shape)
 
 
 def make_samples(eng, seeds, n_lo, n_hi, box_shape, boxes_per_phantom, rng,
-                 shape=(320, 256, 256), voxel_mm=(2.0, 2.0, 3.0), log=print):
+                 shape=(320, 256, 256), voxel_mm=(2.0, 2.0, 3.0), log=print,
+                 organ_fraction=0.0):
     """(x0, target) device tensors of `boxes_per_phantom` boxes of each
-    phantom of `seeds`."""
+    phantom of `seeds`.  The next phantom is generated on a host thread while
+    the GPU runs the current one."""
+    from concurrent.futures import ThreadPoolExecutor
     t = eng.torch
     dev = eng.device
     samples = []
-    for s in seeds:
-        t0 = time.perf_counter()
-        prob = P.patient_phantom(shape=shape, voxel_mm=voxel_mm, seed=int(s))
-        t1 = time.perf_counter()
-        eng.set_problem(PID_A, prob)
-        lo = _run_map(eng, PID_A, n_lo, int(s) + 10 ** 6)
-        B.nmd_reset_tallies(eng.ctx, PID_A)
-        hi = _run_map(eng, PID_A, n_hi, int(s) + 2 * 10 ** 6)
-        inp = eng.inputs[PID_A]
-        for _ in range(boxes_per_phantom):
-            box = pick_box(prob.label, box_shape, rng)
-            x0 = t.empty(tuple(box_shape) + (DN.IN_CH,), dtype=t.bfloat16, device=dev)
-            tgt = t.empty(tuple(box_shape), dtype=t.float32, device=dev)
-            scale = t.empty(2, dtype=t.float64, device=dev)
-            B.nmd_nn_prepare(eng.ctx, prob.shape, box, lo, hi, inp["density"], inp["activity"],
-                             inp["label"], x0, tgt, scale)
-            samples.append((x0, tgt))
-        eng.sync()
-        log("phantom %d: generated in %.1f s, Monte Carlo %.1f s" % (
-            s, t1 - t0, time.perf_counter() - t1))
+    seeds = [int(s) for s in seeds]
+    gen = lambda s: P.patient_phantom(shape=shape, voxel_mm=voxel_mm, seed=s)  # noqa: E731
+    with ThreadPoolExecutor(1) as pool:
+        nxt = pool.submit(gen, seeds[0]) if seeds else None
+        for k, s in enumerate(seeds):
+            t0 = time.perf_counter()
+            prob = nxt.result()
+            if k + 1 < len(seeds):
+                nxt = pool.submit(gen, seeds[k + 1])
+            t1 = time.perf_counter()
+            eng.set_problem(PID_A, prob)
+            lo = _run_map(eng, PID_A, n_lo, s + 10 ** 6)
+            B.nmd_reset_tallies(eng.ctx, PID_A)
+            hi = _run_map(eng, PID_A, n_hi, s + 2 * 10 ** 6)
+            inp = eng.inputs[PID_A]
+            for _ in range(boxes_per_phantom):
+                box = pick_box(prob.label, box_shape, rng, organ_fraction, prob.n_organs)
+                x0 = t.empty(tuple(box_shape) + (DN.IN_CH,), dtype=t.bfloat16, device=dev)
+                tgt = t.empty(tuple(box_shape), dtype=t.float32, device=dev)
+                scale = t.empty(2, dtype=t.float64, device=dev)
+                B.nmd_nn_prepare(eng.ctx, prob.shape, box, lo, hi, inp["density"],
+                                 inp["activity"], inp["label"], x0, tgt, scale)
+                samples.append((x0, tgt))
+            eng.sync()
+            log("phantom %d: waited %.1f s for the host generator, Monte Carlo %.1f s" % (
+                s, t1 - t0, time.perf_counter() - t1))
     return samples
 
 
-def train(eng, net, samples, steps, lr=1e-3, seed=0, log_every=100, log=print):
+def train(eng, net, samples, steps, lr=1e-3, seed=0, log_every=100, log=print,
+          weight_floor=0.0):
     """Adam on randomly drawn samples with a cosine learning-rate decay;
     returns the logged (step, loss) pairs."""
     rng = np.random.default_rng(seed)
@@ -105,7 +122,7 @@ def train(eng, net, samples, steps, lr=1e-3, seed=0, log_every=100, log=print):
         x0, tgt = samples[int(rng.integers(len(samples)))]
         ws.x0, ws.target = x0, tgt
         lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / steps))
-        net.train_step(ws, max(lr_t, lr * 0.02))
+        net.train_step(ws, max(lr_t, lr * 0.02), weight_floor=weight_floor)
         if it % log_every == 0 or it == steps - 1:
             loss = ws.loss_value(net)
             hist.append((it, loss))
@@ -256,13 +273,17 @@ def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="Train the dose denoiser on engine-generated data")
     ap.add_argument("--train-seeds", type=int, nargs=2, default=(10000, 10032))
-    ap.add_argument("--eval-seeds", type=int, nargs=2, default=(20000, 20004))
+    ap.add_argument("--eval-seeds", type=int, nargs=2, default=(20100, 20116))
     ap.add_argument("--n-lo", type=float, default=1e7)
     ap.add_argument("--n-hi", type=float, default=1e9)
     ap.add_argument("--boxes", type=int, default=4)
     ap.add_argument("--box", type=int, nargs=3, default=(160, 128, 128))
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--weight-floor", type=float, default=0.2,
+                    help="loss weight 1/max(target, floor); 0 = plain MSE")
+    ap.add_argument("--organ-boxes", type=float, default=0.5,
+                    help="fraction of boxes centred on an organ voxel")
     ap.add_argument("--out", default="denoiser_weights.npz")
     ap.add_argument("--report", default="denoiser_report.json")
     a = ap.parse_args(argv)
@@ -271,12 +292,12 @@ def main(argv=None):
     rng = np.random.default_rng(a.train_seeds[0])
     log = lambda m: print(m, flush=True)  # noqa: E731
     samples = make_samples(eng, range(*a.train_seeds), int(a.n_lo), int(a.n_hi), tuple(a.box),
-                           a.boxes, rng, log=log)
-    hist = train(eng, net, samples, a.steps, a.lr, log=log)
+                           a.boxes, rng, log=log, organ_fraction=a.organ_boxes)
+    hist = train(eng, net, samples, a.steps, a.lr, log=log, weight_floor=a.weight_floor)
     del samples
     rows = evaluate(eng, net, range(*a.eval_seeds), int(a.n_lo), int(a.n_hi), log=log)
     bias = bias_table(rows)
-    net.save(a.out)
+    net.save(a.out, bias=bias)
     with open(a.report, "w") as f:
         json.dump({"history": hist, "eval": rows, "bias": bias.tolist(), "args": vars(a)}, f)
     log("saved %s and %s" % (a.out, a.report))

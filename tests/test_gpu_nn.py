@@ -203,7 +203,8 @@ def test_pool_and_combine(engine):
         _f64(bfine)[..., 32:48].abs() + U.upsample2(_f64(ycoarse)).abs() / 8))
 
 
-def test_head_loss(engine):
+@pytest.mark.parametrize("floor", [0.0, 0.3])
+def test_head_loss(engine, floor):
     g = torch.Generator().manual_seed(12)
     dev = engine.device
     nvox = 5000
@@ -212,26 +213,31 @@ def test_head_loss(engine):
     tgt = torch.rand(nvox, generator=g)
     hw = torch.randn(16, generator=g) * 0.2
     hb = torch.randn(1, generator=g) * 0.1
+    feat_d, x0_d, tgt_d, hw_d, hb_d = (t.to(dev) for t in (feat, x0, tgt, hw, hb))
     dfeat = torch.empty(nvox, 16, dtype=torch.bfloat16, device=dev)
     grad = torch.empty(18, dtype=torch.float32, device=dev)
-    B.nmd_nn_head_loss(engine.ctx, nvox, feat.to(dev), x0.to(dev), tgt.to(dev), hw.to(dev),
-                       hb.to(dev), dfeat, grad)
+    B.nmd_nn_head_loss(engine.ctx, nvox, feat_d, x0_d, tgt_d, hw_d, hb_d, dfeat, grad, floor)
     engine.sync()
     f = _f64(feat)
+    t64 = tgt.to(F64)
     pred = _f64(x0)[:, 0] + f @ hw.to(F64) + hb.to(F64)
-    e = pred - tgt.to(F64)
-    gv = 2 * e / nvox
+    e = pred - t64
+    wv = 1.0 / torch.clamp(t64, min=floor) if floor > 0 else torch.ones_like(t64)
+    gv = 2 * wv * e / nvox
     gf = (gv[:, None] * hw.to(F64)) * (f > 0)
-    # FP32 error of the residual e, carried into g = 2e/nvox and g*w
-    sc = _f64(x0)[:, 0].abs() + f.abs() @ hw.abs().to(F64) + hb.abs().to(F64) + tgt.abs().to(F64)
-    de = 24 * U24 * sc
-    tol = 2.0 ** -8 * gf.abs() + (2.0 / nvox) * (de[:, None] + 4 * U24 * e.abs()[:, None]) * hw.abs().to(F64)
+    # FP32 error of the residual e (and one rounding of the weight), carried
+    # into g = 2 w e / nvox and g * w_head
+    sc = _f64(x0)[:, 0].abs() + f.abs() @ hw.abs().to(F64) + hb.abs().to(F64) + t64.abs()
+    de = (24 * U24 * sc + 4 * U24 * e.abs()) * wv
+    tol = 2.0 ** -8 * gf.abs() + (2.0 / nvox) * de[:, None] * hw.abs().to(F64)
     assert torch.all((_f64(dfeat) - gf).abs() <= tol)
     gr = _f64(grad)
     gabs = ((gv.abs() + 2 * de / nvox)[:, None] * f.abs()).sum(0)
     assert torch.all((gr[:16] - (gv[:, None] * f).sum(0)).abs() <= 1e-4 * gabs)
     assert abs(gr[16].item() - gv.sum().item()) <= 1e-4 * (gv.abs() + 2 * de / nvox).sum().item()
-    assert abs(gr[17].item() - (e * e).sum().item()) <= 1e-5 * (e * e).sum().item()
+    lref = (wv * e * e).sum().item()
+    assert abs(gr[17].item() - lref) <= 1e-5 * lref
+    assert abs(U.mse(pred[None], tgt[None], floor).item() - lref / nvox) <= 1e-12 * lref
 
 
 def test_adam_step(engine):

@@ -154,3 +154,13 @@ def test_normalise_sets_body_means_to_one():
     assert abs(x[0, ..., 2][body].mean().item() - 1) < 1e-13
     assert torch.allclose(x[0, ..., 1], torch.full((6, 7, 8), float(np.float32(1.85)) / 1.85, dtype=F64))
     assert abs(s - dose[lab > 0].mean()) < 1e-13 * s
+
+
+def test_weighted_loss_reduces_to_the_plain_one():
+    """w = 1/max(t, floor): a floor above every target gives mse/floor; a
+    floor below every target gives the mean of (p - t)^2 / t."""
+    rng = np.random.default_rng(11)
+    p = torch.from_numpy(rng.uniform(0, 2, 1000))
+    t = torch.from_numpy(rng.uniform(0.5, 1.5, 1000))
+    assert abs(U.mse(p, t, 2.0).item() - U.mse(p, t).item() / 2.0) <= 1e-15
+    assert abs(U.mse(p, t, 0.1).item() - (((p - t) ** 2) / t).mean().item()) <= 1e-15
