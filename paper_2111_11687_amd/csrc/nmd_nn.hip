@@ -247,7 +247,9 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   constexpr int DPAIRS = WTX * WTY * WTZ / 2;         // 64
   constexpr int NDI = DPAIRS * (COUT / 8);
   constexpr int NDL = (NDI + 255) / 256;
-  __shared__ __align__(16) uint16_t s_x[CC * WCP];
+  // channel CC of s_x stays zero: padding columns of the last column block
+  // read it, so their B fragments are zero without a per-lane mask
+  __shared__ __align__(16) uint16_t s_x[(CC + 1) * WCP];
   __shared__ __align__(16) uint16_t s_dp[COUT * WDP];
 
   const int vg = blockIdx.x;
@@ -271,19 +273,22 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
 #pragma unroll
     for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
+  for (int i = threadIdx.x; i < WCP; i += 256) s_x[CC * WCP + i] = 0;
+
   // this lane's column of each of the wave's column blocks: LDS offset of
-  // (channel, tap row) and the x shift of the tap
-  int coloff[NBW], colsh[NBW];
-  bool colok[NBW];
+  // (channel, tap row), and the byte selector of v_perm_b32 that shifts the
+  // 10 loaded elements by the tap's x offset (0, 1 or 2 elements)
+  int coloff[NBW];
+  uint32_t colsel[NBW];
 #pragma unroll
   for (int j = 0; j < NBW; ++j) {
     const int nbk = (cg * 4 + wave) * NBW + j;
     const int q = nbk * 16 + lx;
     const int tap = q / CC, ci = q - tap * CC;
-    colok[j] = nbk < NB && tap < 27;
-    const int tp = colok[j] ? tap : 0;
-    coloff[j] = (colok[j] ? ci : 0) * WCP + ((tp / 9) * WHY + (tp / 3) % 3) * WXP;
-    colsh[j] = tp % 3;
+    const bool ok = nbk < NB && tap < 27;
+    const int tp = ok ? tap : 0;
+    coloff[j] = (ok ? ci : CC) * WCP + ((tp / 9) * WHY + (tp / 3) % 3) * WXP;
+    colsel[j] = 0x03020100u + (uint32_t)(tp % 3) * 0x02020202u;
   }
 
   // registers holding the next tile while the current one is computed
@@ -389,15 +394,11 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
         const uint16_t *pb = s_x + coloff[j] + rowo;
         const u32x4_t lo = *reinterpret_cast<const u32x4_t *>(pb);
         const uint32_t hi = *reinterpret_cast<const uint32_t *>(pb + 8);
-        const uint32_t d[5] = {lo.x, lo.y, lo.z, lo.w, hi};
-        uint32_t o4[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t s1 = (d[k] >> 16) | (d[k + 1] << 16);
-          o4[k] = colsh[j] == 0 ? d[k] : (colsh[j] == 1 ? s1 : d[k + 1]);
-        }
-        u32x4_t bv = u32x4_t{o4[0], o4[1], o4[2], o4[3]};
-        if (!colok[j]) bv = u32x4_t{0u, 0u, 0u, 0u};
+        // word k of the shifted fragment: bytes sel of the pair (d[k+1]:d[k])
+        const u32x4_t bv = {__builtin_amdgcn_perm(lo.y, lo.x, colsel[j]),
+                            __builtin_amdgcn_perm(lo.z, lo.y, colsel[j]),
+                            __builtin_amdgcn_perm(lo.w, lo.z, colsel[j]),
+                            __builtin_amdgcn_perm(hi, lo.w, colsel[j])};
 #pragma unroll
         for (int i = 0; i < NCBO; ++i) acc[i][j] = mfma_bf16(av[i], bv, acc[i][j]);
       }
@@ -409,10 +410,10 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
   float *out = a.part + (size_t)vg * COUT * ke;
 #pragma unroll
   for (int j = 0; j < NBW; ++j) {
-    if (!colok[j]) continue;
     const int nbk = (cg * 4 + wave) * NBW + j;
     const int q = nbk * 16 + lx;
     const int tap = q / CC, ci = q - tap * CC;
+    if (nbk >= NB || tap >= 27) continue;
     const size_t k = (size_t)tap * a.cin + cbase + ci;
 #pragma unroll
     for (int i = 0; i < NCBO; ++i)
