@@ -390,9 +390,32 @@ def bench_organ_time(args):
             eng, prob, 10 ** 7, seed + 3 * 10 ** 6, tol=tol, max_decays=2 * 10 ** 10)
         dn = T.organ_dose_with_fallback(eng, net, prob, 10 ** 7, seed + 4 * 10 ** 6, bias,
                                         tol=tol, ws=ws, max_decays=2 * 10 ** 10)
+        # voxel level (untimed): the 10^7 map and its denoised version
+        eng.set_problem(T.PID_A, prob)
+        eng.run(T.PID_A, 10 ** 7, seed + 10 ** 6)
+        lo_map, _ = eng.dose(T.PID_A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dn_map = T.denoise_map(eng, net, T.PID_A, prob, lo_map, ws)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        lo_h, dn_h = lo_map.cpu().numpy(), dn_map.cpu().numpy()
+        del lo_map, dn_map
         eng.set_problem(T.PID_A, prob)
         eng.run(T.PID_A, 10 ** 9, seed + 2 * 10 ** 6)
         ref, _, ref_sig = eng.organs(T.PID_A)
+        ref_map, ref_rel = eng.dose(T.PID_A)
+        ref_h, rel_h = ref_map.cpu().numpy(), ref_rel.cpu().numpy()
+        del ref_map, ref_rel
+        body = prob.label > 0
+        m = body & (ref_h > 0.1 * ref_h[body].mean())
+        rms = lambda x: float(np.sqrt(np.mean(((x[m] - ref_h[m]) / ref_h[m]) ** 2)))  # noqa: E731
+        e_lo_v, e_dn_v = rms(lo_h), rms(dn_h)
+        e_ref_v = float(np.sqrt(np.mean(rel_h[m] ** 2)))
+        # Monte Carlo voxel error falls as N^-1/2: decays plain MC needs for
+        # the denoised map's error, the reference's own noise taken out
+        num, den = e_lo_v ** 2 - e_ref_v ** 2, e_dn_v ** 2 - e_ref_v ** 2
+        n_eq = 10 ** 7 * num / den if den > 0 else float("inf")
         present = ref > 0  # organs with at least one voxel in this phantom
         e_mc = np.abs(mc_org - ref)[present] / ref[present]
         e_dn = np.abs(dn["organ"] - ref)[present] / ref[present]
@@ -402,7 +425,10 @@ def bench_organ_time(args):
                "organs_from_denoiser": int(sum(1 for x in dn["source"] if x == "denoiser")),
                "mc_max_err": float(e_mc.max()), "dn_max_err": float(e_dn.max()),
                "ref_max_sigma": float(ref_sig[present].max()),
-               "organs_present": int(present.sum())}
+               "organs_present": int(present.sum()),
+               "voxel_rms_rel_err_mc1e7": e_lo_v, "voxel_rms_rel_err_denoised": e_dn_v,
+               "voxel_rms_rel_sigma_ref1e9": e_ref_v, "voxel_equivalent_mc_decays": n_eq,
+               "inference_s": t_inf}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
     t_mc = float(np.mean([r["mc_s"] for r in rows]))
@@ -416,7 +442,10 @@ def bench_organ_time(args):
         "config": {"workload": "held-out patient phantoms 256x256x320 (seeds 20008+), 27 "
                                "organs; plain MC until 2 sigma <= 1% for every organ vs 10^7 "
                                "decays + U-Net denoiser + MC judge and fallback",
-                   "mc_seconds": t_mc, "mc_denoiser_seconds": t_dn, "phantoms": rows},
+                   "mc_seconds": t_mc, "mc_denoiser_seconds": t_dn,
+                   "voxel_equivalent_mc_decays": float(np.median(
+                       [r["voxel_equivalent_mc_decays"] for r in rows])),
+                   "phantoms": rows},
     }
     eng.close()
     print(json.dumps(out), flush=True)

@@ -272,17 +272,17 @@ def organ_dose_with_fallback(eng, net, prob, n_lo, seed, bias, tol=0.01, max_dec
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="Train the dose denoiser on engine-generated data")
-    ap.add_argument("--train-seeds", type=int, nargs=2, default=(10000, 10032))
-    ap.add_argument("--eval-seeds", type=int, nargs=2, default=(20100, 20116))
+    ap.add_argument("--train-seeds", type=int, nargs=2, default=(10000, 10064))
+    ap.add_argument("--eval-seeds", type=int, nargs=2, default=(20000, 20008))
     ap.add_argument("--n-lo", type=float, default=1e7)
     ap.add_argument("--n-hi", type=float, default=1e9)
     ap.add_argument("--boxes", type=int, default=4)
     ap.add_argument("--box", type=int, nargs=3, default=(160, 128, 128))
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--weight-floor", type=float, default=0.2,
+    ap.add_argument("--weight-floor", type=float, default=0.0,
                     help="loss weight 1/max(target, floor); 0 = plain MSE")
-    ap.add_argument("--organ-boxes", type=float, default=0.5,
+    ap.add_argument("--organ-boxes", type=float, default=0.0,
                     help="fraction of boxes centred on an organ voxel")
     ap.add_argument("--out", default="denoiser_weights.npz")
     ap.add_argument("--report", default="denoiser_report.json")
