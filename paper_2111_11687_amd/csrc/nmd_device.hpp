@@ -47,13 +47,17 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 
 // Random stream of one history: counter (block, hid_lo, hid_hi, phantom),
 // key (seed_lo, seed_hi); the words of each block are handed out in order.
-// Up to five words are buffered in b0..b4 and consumed from b0 with a shift,
+// Up to eight words are buffered in b0..b7 and consumed from b0 with a shift,
 // so no word is ever selected by a run-time index (which would put the
-// buffer in scratch memory).
+// buffer in scratch memory).  Blocks are generated ahead of use where a
+// phase knows its draws -- two at the start of a history, one before the
+// two draws of a flight step or the first draws of an interaction -- so
+// that all lanes of the phase refill together instead of one call site at a
+// time.  Generating ahead never changes which word a draw returns.
 template <bool kCount>
 struct Stream {
   uint32_t k0, k1, h0, h1, pid, blk;
-  uint32_t b0, b1, b2, b3, b4;
+  uint32_t b0, b1, b2, b3, b4, b5, b6, b7;
   uint32_t pos;      // words buffered
   uint32_t n_drawn;  // uniforms handed out (debug records only)
 
@@ -64,29 +68,34 @@ struct Stream {
     h0 = (uint32_t)hid;
     h1 = (uint32_t)(hid >> 32);
     pid = p;
-    blk = 0;
-    pos = 0;
+    philox4x32_10<true>(0u, h0, h1, pid, k0, k1, b0, b1, b2, b3);
+    philox4x32_10<true>(1u, h0, h1, pid, k0, k1, b4, b5, b6, b7);
+    blk = 2;
+    pos = 8;
     n_drawn = 0;
   }
-  // Make sure at least two words are buffered (one block is appended).
+  // Append the next block after the pos buffered words (pos <= 4).
+  __device__ __forceinline__ void append() {
+    uint32_t n0, n1, n2, n3;
+    philox4x32_10<true>(blk, h0, h1, pid, k0, k1, n0, n1, n2, n3);
+    ++blk;
+    const uint32_t q = pos;
+    b0 = q == 0 ? n0 : b0;
+    b1 = q == 0 ? n1 : (q == 1 ? n0 : b1);
+    b2 = q == 0 ? n2 : (q == 1 ? n1 : (q == 2 ? n0 : b2));
+    b3 = q == 0 ? n3 : (q == 1 ? n2 : (q == 2 ? n1 : (q == 3 ? n0 : b3)));
+    b4 = q == 1 ? n3 : (q == 2 ? n2 : (q == 3 ? n1 : (q == 4 ? n0 : b4)));
+    b5 = q == 2 ? n3 : (q == 3 ? n2 : (q == 4 ? n1 : b5));
+    b6 = q == 3 ? n3 : (q == 4 ? n2 : b6);
+    b7 = q == 4 ? n3 : b7;
+    pos = q + 4;
+  }
+  // Make sure at least two (four) words are buffered.
   __device__ __forceinline__ void reserve2() {
-    if (pos < 2) {
-      uint32_t n0, n1, n2, n3;
-      philox4x32_10<true>(blk, h0, h1, pid, k0, k1, n0, n1, n2, n3);
-      ++blk;
-      if (pos == 0) {
-        b0 = n0;
-        b1 = n1;
-        b2 = n2;
-        b3 = n3;
-      } else {
-        b1 = n0;
-        b2 = n1;
-        b3 = n2;
-        b4 = n3;
-      }
-      pos += 4;
-    }
+    if (pos < 2) append();
+  }
+  __device__ __forceinline__ void reserve4() {
+    if (pos < 4) append();
   }
   // Next word; the caller guarantees one is buffered.
   __device__ __forceinline__ uint32_t take() {
@@ -95,6 +104,9 @@ struct Stream {
     b1 = b2;
     b2 = b3;
     b3 = b4;
+    b4 = b5;
+    b5 = b6;
+    b6 = b7;
     --pos;
     if (kCount) ++n_drawn;
     return x;

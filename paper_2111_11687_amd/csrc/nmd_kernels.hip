@@ -36,6 +36,24 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
+
+// Address-space views.  Descriptor reads go through the constant space:
+// they become scalar loads, which are neither repeated after every store
+// (the compiler cannot otherwise rule out that a tally atomic hits the
+// descriptor table) nor ordered behind the vector-memory counter; the table
+// is not written while a launch runs.  Tallies, deposit lists, records and
+// the queue go through the global space, so they compile to global_*
+// instructions; flat_* ones would also count against the LDS counter and
+// make every LDS wait wait for them.
+typedef const __attribute__((address_space(4))) PhantomDesc CDesc;
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *G(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gadd(T *p, T v) {
+  __hip_atomic_fetch_add(G(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -147,40 +165,40 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   unsigned long long cur_next = 0, cur_end = 0, pend_next = 0, pend_end = 0;
   int pend_p = -1;
   bool qdone = false;
-  const PhantomDesc *D = P.desc;
+  CDesc *D = (CDesc *)P.desc;
   unsigned long long hid0 = 0;
 
   auto flush_wave = [&]() {
     if (wp < 0) return;
-    const PhantomDesc *d = D;
+    CDesc *d = D;
     if (lane >= 1 && lane < 6) {
       const double x = wa.ledger[lane];
-      if (x != 0.0) atomicAdd(&d->ledger[lane], x);
+      if (x != 0.0) gadd(&d->ledger[lane], x);
       wa.ledger[lane] = 0.0;
     }
     if (lane < kStatN) {
       const unsigned long long x = wa.stat[lane];
       if (lane == 9)
-        atomicMax(&d->stats[9], x);
+        __hip_atomic_fetch_max(G(&d->stats[9]), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       else if (x)
-        atomicAdd(&d->stats[lane], x);
+        gadd(&d->stats[lane], x);
       wa.stat[lane] = 0ull;
     }
     const int n_slots = d->n_org + 1;
     for (int i = lane; i < n_slots; i += 64) {
       const double2 o = wl.org[i];
       if (o.x != 0.0 || o.y != 0.0) {
-        atomicAdd(&d->organ[i].x, o.x);
-        atomicAdd(&d->organ[i].y, o.y);
+        gadd(&d->organ[i].x, o.x);
+        gadd(&d->organ[i].y, o.y);
       }
     }
   };
 
   // load the wave's per-phantom LDS tables
   auto enter_phantom = [&]() {
-    for (int i = lane; i < kNGrid; i += 64) wl.maj[i] = D->ln2_major[i];
+    for (int i = lane; i < kNGrid; i += 64) wl.maj[i] = G(D->ln2_major)[i];
     for (int i = lane; i <= D->n_org; i += 64) {
-      wl.w[i] = D->organ_w[i];
+      wl.w[i] = G(D->organ_w)[i];
       wl.org[i] = make_double2(0.0, 0.0);
     }
     wave_lds_sync();
@@ -217,7 +235,9 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       const uint32_t x = st.word();
       const uint32_t j = __umulhi(x, D->n_alias);
       const float ua = st.uniform();
-      const uint4 a = D->alias[j];
+      typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+      const u32x4v av = G(reinterpret_cast<const u32x4v *>(D->alias))[j];
+      const uint4 a = make_uint4(av.x, av.y, av.z, av.w);
       const uint32_t c = ua < __uint_as_float(a.x) ? a.y : a.z;  // x | y << 10 | z << 20
       const uint32_t ix = c & 1023u, iy = (c >> 10) & 1023u, iz = c >> 20;
       o0 = ((float)ix + st.uniform()) * D->dx;
@@ -242,13 +262,13 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   // Score the history's merged deposits: voxel sums S, S2 and the
   // per-history organ scores q_o = sum_{v in o} e_v c / (m_v N_o).
   auto flush_list = [&](bool final_flush) {
-    const PhantomDesc *d = D;
+    CDesc *d = D;
     double edep = 0.0, sumv = 0.0;
 #pragma unroll
     for (int i = 0; i < kRegDep; ++i) {
       if ((uint32_t)i < cnt) {
-        atomicAdd(&d->tally[rv[i]].x, re[i]);
-        atomicAdd(&d->tally[rv[i]].y, re[i] * re[i]);
+        gadd(&d->tally[rv[i]].x, re[i]);
+        gadd(&d->tally[rv[i]].y, re[i] * re[i]);
         if (kDebug) {
           edep += re[i];
           sumv += (double)rv[i];
@@ -257,10 +277,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     }
     for (uint32_t j = kRegDep; j < cnt; ++j) {
       const uint32_t idx = j * L + gl;
-      const uint32_t v = P.dep_v[idx];
-      const double e = P.dep_e[idx];
-      atomicAdd(&d->tally[v].x, e);
-      atomicAdd(&d->tally[v].y, e * e);
+      const uint32_t v = G(P.dep_v)[idx];
+      const double e = G(P.dep_e)[idx];
+      gadd(&d->tally[v].x, e);
+      gadd(&d->tally[v].y, e * e);
       if (kDebug) {
         edep += e;
         sumv += (double)v;
@@ -294,28 +314,28 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
 #pragma unroll
         for (int i = 0; i < kRegDep; ++i) {
           const uint32_t idx = (uint32_t)i * L + gl;
-          P.dep_v[idx] = rv[i];
-          P.dep_e[idx] = re[i];
-          P.dep_r[idx] = rr[i];
+          G(P.dep_v)[idx] = rv[i];
+          G(P.dep_e)[idx] = re[i];
+          G(P.dep_r)[idx] = rr[i];
         }
         for (uint32_t j = 0; j < cnt; ++j) {
           const uint32_t idx = j * L + gl;
-          const uint32_t r = P.dep_r[idx];
+          const uint32_t r = G(P.dep_r)[idx];
           const uint32_t oo = r >> 8;
-          P.dep_v[idx] = oo;
-          P.dep_e[idx] = P.dep_e[idx] * wl.w[oo] * s_irho[r & 0xFFu];
+          G(P.dep_v)[idx] = oo;
+          G(P.dep_e)[idx] = G(P.dep_e)[idx] * wl.w[oo] * s_irho[r & 0xFFu];
         }
         unsigned long long used = 0ull;
         for (uint32_t i = 0; i < cnt; ++i) {
           if ((used >> i) & 1ull) continue;
           const uint32_t ii = i * L + gl;
-          const uint32_t oo = P.dep_v[ii];
+          const uint32_t oo = G(P.dep_v)[ii];
           if (oo == 0) continue;
-          double s = P.dep_e[ii];
+          double s = G(P.dep_e)[ii];
           for (uint32_t j = i + 1; j < cnt; ++j) {
             const uint32_t jj = j * L + gl;
-            if (P.dep_v[jj] == oo) {
-              s += P.dep_e[jj];
+            if (G(P.dep_v)[jj] == oo) {
+              s += G(P.dep_e)[jj];
               used |= 1ull << j;
             }
           }
@@ -358,8 +378,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     if (cnt > (uint32_t)kRegDep) {
       for (uint32_t j = kRegDep; j < cnt; ++j) {
         const uint32_t idx = j * L + gl;
-        if (P.dep_v[idx] == v) {
-          P.dep_e[idx] += e;
+        if (G(P.dep_v)[idx] == v) {
+          G(P.dep_e)[idx] += e;
           return;
         }
       }
@@ -368,15 +388,15 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       // list full (not reached on the phantoms here; counted): score this
       // deposit on its own, which splits the history's square for voxel v
       atomicAdd(&wa.stat[11], 1ull);
-      atomicAdd(&D->tally[v].x, e);
-      atomicAdd(&D->tally[v].y, e * e);
+      gadd(&D->tally[v].x, e);
+      gadd(&D->tally[v].y, e * e);
       return;
     }
     if (cnt >= (uint32_t)kRegDep) {
       const uint32_t idx = cnt * L + gl;
-      P.dep_v[idx] = rv[kRegDep - 1];
-      P.dep_e[idx] = re[kRegDep - 1];
-      P.dep_r[idx] = rr[kRegDep - 1];
+      G(P.dep_v)[idx] = rv[kRegDep - 1];
+      G(P.dep_e)[idx] = re[kRegDep - 1];
+      G(P.dep_r)[idx] = rr[kRegDep - 1];
     }
 #pragma unroll
     for (int i = kRegDep - 1; i > 0; --i) {
@@ -401,8 +421,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         // switch phantom once every lane of the wave has finished
         flush_wave();
         wp = pend_p;
-        D = P.desc + P.slot[wp].id;
-        hid0 = *D->n_done;  // histories already run on this phantom
+        D = (CDesc *)(P.desc + P.slot[wp].id);
+        hid0 = *G(D->n_done);  // histories already run on this phantom
         cur_next = pend_next;
         cur_end = pend_end;
         pend_p = -1;
@@ -419,9 +439,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       if (pend_p >= 0 || qdone) break;
       unsigned long long c = 0;
       if (lane == (uint32_t)(__ffsll((long long)__ballot(1)) - 1)) {
-        c = atomicAdd(&P.queue[0], 1ull);
+        c = __hip_atomic_fetch_add(G(&P.queue[0]), 1ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         if (P.abort_after && c >= P.abort_after) {
-          atomicExch(&P.queue[1], 1ull);
+          __hip_atomic_exchange(G(&P.queue[1]), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           c = P.total_chunks;
         }
       }
@@ -436,7 +457,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       const unsigned long long first = (c - P.slot[p].chunk0) * (unsigned long long)P.chunk;
       unsigned long long last = first + P.chunk;
       last = last < P.slot[p].n_hist ? last : P.slot[p].n_hist;
-      if (lane == 0) atomicAdd(&P.desc[P.slot[p].id].stats[12], 1ull);
+      if (lane == 0) gadd(&P.desc[P.slot[p].id].stats[12], 1ull);
       if (p == wp) {
         cur_next = first;
         cur_end = last;
@@ -464,6 +485,9 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       // ---- interactions at the collision points found by the flights
       if (state == kInteract) {
         ++n_real;
+        // the first Klein-Nishina attempt and the azimuth (or the Rayleigh
+        // pair): generated here for all interacting lanes at once
+        if (ev_t != 2) st.reserve4();
         bool pdone = false;
         double dep = -1.0;  // energy left in voxel ev_v by this event
         if (ev_t == 1) {
@@ -558,7 +582,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         } else {
           const uint32_t v =
               (uint32_t)fx + (uint32_t)D->nx * ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz);
-          const uint32_t r16 = D->rec[v];
+          const uint32_t r16 = G(D->rec)[v];
           const float4 pal = s_pal[r16 & 0xFFu];
           const float mc = pal.x * ep.sig;
           const float mpe = pal.y * ep.gpe;
