@@ -159,7 +159,8 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
     __syncthreads();
     const uint16_t *wrow = a.w + (size_t)lx * 27 * a.cin + ch * CC;
     const size_t wcb = (size_t)16 * 27 * a.cin;  // one column block of weights
-    for (int s = 0; s < NS; ++s) {
+    // fragments of K step s: A from the LDS halo, B from the weight array
+    auto load_step = [&](int s, u32x4_t (&av)[4], u32x4_t (&b)[NCB]) {
       const int p = 4 * s + g;
       const bool valid = p < NP;
       const int pp = valid ? p : 0;
@@ -167,20 +168,40 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
       const int kz = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
       const int aoff = ((kz * HY + ky) * HX + kx) * P + c8 * 8;
       const int woff = tap * a.cin + c8 * 8;
-      u32x4_t b[NCB];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         b[cb] = *reinterpret_cast<const u32x4_t *>(wrow + cb * wcb + woff);
         if (!valid) b[cb] = u32x4_t{0u, 0u, 0u, 0u};
       }
-      u32x4_t av[4];
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
         av[rb] = *reinterpret_cast<const u32x4_t *>(s_x + rowoff[rb] + aoff);
+    };
+    // software pipeline: step s + 1's fragments load during step s's MFMAs
+    u32x4_t av[4], b[NCB], avn[4], bn[NCB];
+    load_step(0, av, b);
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);    // step 0: DS reads
+    __builtin_amdgcn_sched_group_barrier(0x020, NCB, 0);  // step 0: VMEM reads
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (s + 1 < NS) load_step(s + 1, avn, bn);
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mfma_bf16(av[rb], b[cb], acc[rb][cb]);
+      // keep that order: the next step's LDS and global reads go out before
+      // this step's MFMAs, so their latency hides behind them
+      if (s + 1 < NS) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);    // DS reads
+        __builtin_amdgcn_sched_group_barrier(0x020, NCB, 0);  // VMEM reads
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 4 * NCB, 0);  // MFMA
+      if (s + 1 < NS) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) av[rb] = avn[rb];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = bn[cb];
+      }
     }
   }
 
