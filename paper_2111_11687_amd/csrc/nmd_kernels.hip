@@ -116,6 +116,12 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   __shared__ float s_kn[kNGrid];
   __shared__ WaveAcc s_acc[kWavesPerBlock];
   __shared__ float s_start[kWavesPerBlock][6][64];  // decay point and first direction
+  // list positions kRegDep .. kRegDep + kLdsDep - 1 of each lane's deposit
+  // list (lane fastest, so a wave's accesses to one position are
+  // conflict-free); positions beyond them are in global memory
+  __shared__ uint32_t s_lv[kWavesPerBlock][kLdsDep][64];  // voxel
+  __shared__ uint16_t s_lr[kWavesPerBlock][kLdsDep][64];  // voxel record
+  __shared__ double s_le[kWavesPerBlock][kLdsDep][64];    // energy
   extern __shared__ double2 s_dyn[];
 
   const uint32_t tid = threadIdx.x;
@@ -126,6 +132,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   WaveAcc &wa = s_acc[wave];
   const WaveLds wl = wave_lds(s_dyn, wave, P.n_slots);
   float(&sst)[6][64] = s_start[wave];
+  uint32_t(&lv)[kLdsDep][64] = s_lv[wave];
+  uint16_t(&lr)[kLdsDep][64] = s_lr[wave];
+  double(&le)[kLdsDep][64] = s_le[wave];
+  constexpr uint32_t kTier = kRegDep + kLdsDep;  // first list position in global memory
 
   for (int i = tid; i < P.n_pal; i += kBlock) {
     const float4 q = P.palette[i];
@@ -275,8 +285,21 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         }
       }
     }
-    for (uint32_t j = kRegDep; j < cnt; ++j) {
-      const uint32_t idx = j * L + gl;
+#pragma unroll
+    for (int j = 0; j < kLdsDep; ++j) {
+      if ((uint32_t)(kRegDep + j) < cnt) {
+        const uint32_t v = lv[j][lane];
+        const double e = le[j][lane];
+        gadd(&d->tally[v].x, e);
+        gadd(&d->tally[v].y, e * e);
+        if (kDebug) {
+          edep += e;
+          sumv += (double)v;
+        }
+      }
+    }
+    for (uint32_t p = kTier; p < cnt; ++p) {
+      const uint32_t idx = p * L + gl;
       const uint32_t v = G(P.dep_v)[idx];
       const double e = G(P.dep_e)[idx];
       gadd(&d->tally[v].x, e);
@@ -287,14 +310,14 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       }
     }
     if (d->n_org > 0) {
-      if (cnt <= (uint32_t)kRegDep) {
-        // in place: the list registers turn into (organ, score) pairs
+      // the list registers turn into (organ, score) pairs
 #pragma unroll
-        for (int i = 0; i < kRegDep; ++i) {
-          const uint32_t oi = (uint32_t)i < cnt ? rr[i] >> 8 : 0u;
-          re[i] = oi ? re[i] * wl.w[oi] * s_irho[rr[i] & 0xFFu] : 0.0;
-          rr[i] = oi;
-        }
+      for (int i = 0; i < kRegDep; ++i) {
+        const uint32_t oi = (uint32_t)i < cnt ? rr[i] >> 8 : 0u;
+        re[i] = oi ? re[i] * wl.w[oi] * s_irho[rr[i] & 0xFFu] : 0.0;
+        rr[i] = oi;
+      }
+      if (cnt <= (uint32_t)kRegDep) {
 #pragma unroll
         for (int i = 0; i < kRegDep; ++i) {
           bool first = rr[i] != 0;
@@ -309,38 +332,53 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
           }
         }
       } else {
-        // long history: move the register entries next to the overflow
-        // entries and merge organs over the whole list
+        // long history: one scan of the list per distinct organ, each
+        // summing that organ's scores in list order
+        unsigned long long rem = 0ull;  // bit p: position p still to merge
 #pragma unroll
-        for (int i = 0; i < kRegDep; ++i) {
-          const uint32_t idx = (uint32_t)i * L + gl;
-          G(P.dep_v)[idx] = rv[i];
-          G(P.dep_e)[idx] = re[i];
-          G(P.dep_r)[idx] = rr[i];
-        }
-        for (uint32_t j = 0; j < cnt; ++j) {
-          const uint32_t idx = j * L + gl;
-          const uint32_t r = G(P.dep_r)[idx];
-          const uint32_t oo = r >> 8;
-          G(P.dep_v)[idx] = oo;
-          G(P.dep_e)[idx] = G(P.dep_e)[idx] * wl.w[oo] * s_irho[r & 0xFFu];
-        }
-        unsigned long long used = 0ull;
-        for (uint32_t i = 0; i < cnt; ++i) {
-          if ((used >> i) & 1ull) continue;
-          const uint32_t ii = i * L + gl;
-          const uint32_t oo = G(P.dep_v)[ii];
-          if (oo == 0) continue;
-          double s = G(P.dep_e)[ii];
-          for (uint32_t j = i + 1; j < cnt; ++j) {
-            const uint32_t jj = j * L + gl;
-            if (G(P.dep_v)[jj] == oo) {
-              s += G(P.dep_e)[jj];
-              used |= 1ull << j;
+        for (int i = 0; i < kRegDep; ++i) rem |= rr[i] ? 1ull << i : 0ull;
+#pragma unroll
+        for (int j = 0; j < kLdsDep; ++j)
+          if ((uint32_t)(kRegDep + j) < cnt && (lr[j][lane] >> 8)) rem |= 1ull << (kRegDep + j);
+        for (uint32_t p = kTier; p < cnt; ++p)
+          if (G(P.dep_r)[p * L + gl] >> 8) rem |= 1ull << p;
+        while (rem) {
+          uint32_t o = 0u;  // the organ of the first position left
+          double s = 0.0;
+#pragma unroll
+          for (int i = 0; i < kRegDep; ++i) {
+            if ((rem >> i) & 1ull) {
+              o = o ? o : rr[i];
+              if (rr[i] == o) {
+                s += re[i];
+                rem &= ~(1ull << i);
+              }
             }
           }
-          atomicAdd(&wl.org[oo].x, s);
-          atomicAdd(&wl.org[oo].y, s * s);
+#pragma unroll
+          for (int j = 0; j < kLdsDep; ++j) {
+            if ((rem >> (kRegDep + j)) & 1ull) {
+              const uint32_t r = lr[j][lane];
+              o = o ? o : r >> 8;
+              if ((r >> 8) == o) {
+                s += le[j][lane] * wl.w[o] * s_irho[r & 0xFFu];
+                rem &= ~(1ull << (kRegDep + j));
+              }
+            }
+          }
+          for (uint32_t p = kTier; p < cnt; ++p) {
+            if ((rem >> p) & 1ull) {
+              const uint32_t idx = p * L + gl;
+              const uint32_t r = G(P.dep_r)[idx];
+              o = o ? o : r >> 8;
+              if ((r >> 8) == o) {
+                s += G(P.dep_e)[idx] * wl.w[o] * s_irho[r & 0xFFu];
+                rem &= ~(1ull << p);
+              }
+            }
+          }
+          atomicAdd(&wl.org[o].x, s);
+          atomicAdd(&wl.org[o].y, s * s);
         }
       }
     }
@@ -365,7 +403,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   // Add energy e to voxel v (record r16) in the history's deposit list,
   // merged by voxel.  The registers hold the kRegDep most recent distinct
   // voxels (a shift register, so no entry is addressed by a run-time
-  // index); older ones move to the lane's overflow list.
+  // index); the oldest one moves on to the next list position, which is in
+  // LDS for the next kLdsDep positions and in global memory after them.
   auto deposit = [&](uint32_t v, uint32_t r16, double e) {
     bool found = false;
 #pragma unroll
@@ -376,8 +415,16 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     }
     if (found) return;
     if (cnt > (uint32_t)kRegDep) {
-      for (uint32_t j = kRegDep; j < cnt; ++j) {
-        const uint32_t idx = j * L + gl;
+      int hit = -1;
+#pragma unroll
+      for (int j = 0; j < kLdsDep; ++j)
+        if ((uint32_t)(kRegDep + j) < cnt && lv[j][lane] == v) hit = j;
+      if (hit >= 0) {
+        le[hit][lane] += e;
+        return;
+      }
+      for (uint32_t p = kTier; p < cnt; ++p) {
+        const uint32_t idx = p * L + gl;
         if (G(P.dep_v)[idx] == v) {
           G(P.dep_e)[idx] += e;
           return;
@@ -392,11 +439,16 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       gadd(&D->tally[v].y, e * e);
       return;
     }
-    if (cnt >= (uint32_t)kRegDep) {
+    if (cnt >= kTier) {
       const uint32_t idx = cnt * L + gl;
       G(P.dep_v)[idx] = rv[kRegDep - 1];
       G(P.dep_e)[idx] = re[kRegDep - 1];
       G(P.dep_r)[idx] = rr[kRegDep - 1];
+    } else if (cnt >= (uint32_t)kRegDep) {
+      const uint32_t j = cnt - kRegDep;
+      lv[j][lane] = rv[kRegDep - 1];
+      le[j][lane] = re[kRegDep - 1];
+      lr[j][lane] = (uint16_t)rr[kRegDep - 1];
     }
 #pragma unroll
     for (int i = kRegDep - 1; i > 0; --i) {
