@@ -12,8 +12,8 @@ constexpr int kMaxPhantoms = 64;
 constexpr int kMaxPalette = 256;        // u8 voxel records
 constexpr int kNGrid = 256;             // energy nodes, 1 keV .. 511 keV
 constexpr int kDepCap = 64;             // distinct deposit voxels kept per history
-constexpr int kRegDep = 4;              // of which held in registers
-constexpr int kLdsDep = 6;              // the next ones in LDS (the rest in global memory)
+constexpr int kRegDep = 3;              // of which held in registers
+constexpr int kLdsDep = 9;              // the next ones in LDS (the rest in global memory)
 constexpr int kBlock = 256;             // transport workgroup size (4 waves)
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kMaxOrganSlots = 256;     // labels 0..255

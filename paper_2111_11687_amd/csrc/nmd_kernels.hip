@@ -136,6 +136,9 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   uint16_t(&lr)[kLdsDep][64] = s_lr[wave];
   double(&le)[kLdsDep][64] = s_le[wave];
   constexpr uint32_t kTier = kRegDep + kLdsDep;  // first list position in global memory
+  // the global positions go four at a time: a group never passes kDepCap,
+  // so no bit index of a 64-bit position mask reaches 64
+  static_assert(kDepCap <= 64 && (kDepCap - kTier) % 4 == 0, "deposit list tiers");
 
   for (int i = tid; i < P.n_pal; i += kBlock) {
     const float4 q = P.palette[i];
@@ -298,15 +301,27 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         }
       }
     }
-    for (uint32_t p = kTier; p < cnt; ++p) {
-      const uint32_t idx = p * L + gl;
-      const uint32_t v = G(P.dep_v)[idx];
-      const double e = G(P.dep_e)[idx];
-      gadd(&d->tally[v].x, e);
-      gadd(&d->tally[v].y, e * e);
-      if (kDebug) {
-        edep += e;
-        sumv += (double)v;
+    // global positions, four per round trip
+    for (uint32_t p = kTier; p < cnt; p += 4) {
+      uint32_t gv[4];
+      double ge[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool in = p + k < cnt;
+        const uint32_t idx = (in ? p + k : p) * L + gl;
+        gv[k] = G(P.dep_v)[idx];
+        ge[k] = G(P.dep_e)[idx];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (p + k < cnt) {
+          gadd(&d->tally[gv[k]].x, ge[k]);
+          gadd(&d->tally[gv[k]].y, ge[k] * ge[k]);
+          if (kDebug) {
+            edep += ge[k];
+            sumv += (double)gv[k];
+          }
+        }
       }
     }
     if (d->n_org > 0) {
@@ -340,8 +355,14 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
 #pragma unroll
         for (int j = 0; j < kLdsDep; ++j)
           if ((uint32_t)(kRegDep + j) < cnt && (lr[j][lane] >> 8)) rem |= 1ull << (kRegDep + j);
-        for (uint32_t p = kTier; p < cnt; ++p)
-          if (G(P.dep_r)[p * L + gl] >> 8) rem |= 1ull << p;
+        for (uint32_t p = kTier; p < cnt; p += 4) {
+          uint32_t gr[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) gr[k] = G(P.dep_r)[(p + k < cnt ? p + k : p) * L + gl];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (p + k < cnt && (gr[k] >> 8)) rem |= 1ull << (p + k);
+        }
         while (rem) {
           uint32_t o = 0u;  // the organ of the first position left
           double s = 0.0;
@@ -366,14 +387,24 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
               }
             }
           }
-          for (uint32_t p = kTier; p < cnt; ++p) {
-            if ((rem >> p) & 1ull) {
-              const uint32_t idx = p * L + gl;
-              const uint32_t r = G(P.dep_r)[idx];
-              o = o ? o : r >> 8;
-              if ((r >> 8) == o) {
-                s += G(P.dep_e)[idx] * wl.w[o] * s_irho[r & 0xFFu];
-                rem &= ~(1ull << p);
+          for (uint32_t p = kTier; p < cnt; p += 4) {
+            if (((rem >> p) & 0xFull) == 0ull) continue;
+            uint32_t gr[4];
+            double ge[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t idx = (p + k < cnt ? p + k : p) * L + gl;
+              gr[k] = G(P.dep_r)[idx];
+              ge[k] = G(P.dep_e)[idx];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              if ((rem >> (p + k)) & 1ull) {
+                o = o ? o : gr[k] >> 8;
+                if ((gr[k] >> 8) == o) {
+                  s += ge[k] * wl.w[o] * s_irho[gr[k] & 0xFFu];
+                  rem &= ~(1ull << (p + k));
+                }
               }
             }
           }
@@ -423,10 +454,17 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         le[hit][lane] += e;
         return;
       }
-      for (uint32_t p = kTier; p < cnt; ++p) {
-        const uint32_t idx = p * L + gl;
-        if (G(P.dep_v)[idx] == v) {
-          G(P.dep_e)[idx] += e;
+      // global positions, four per round trip
+      for (uint32_t p = kTier; p < cnt; p += 4) {
+        uint32_t gv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gv[k] = G(P.dep_v)[(p + k < cnt ? p + k : p) * L + gl];
+        int ghit = -1;
+#pragma unroll
+        for (int k = 3; k >= 0; --k)
+          if (p + k < cnt && gv[k] == v) ghit = k;
+        if (ghit >= 0) {
+          G(P.dep_e)[(p + ghit) * L + gl] += e;
           return;
         }
       }

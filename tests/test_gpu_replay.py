@@ -40,8 +40,9 @@ def _check(g, o, frac=0.995):
     e_ok = np.abs(g[:, 0] - o[:, 0]) <= 1e-5 + 1e-5 * np.abs(o[:, 0])
     x_ok = np.abs(g[:, 1] - o[:, 1]) <= 1e-5 + 1e-5 * np.abs(o[:, 1])
     assert (same & e_ok & x_ok).mean() >= frac
-    # where the histories agree, the deposit voxels agree too
-    v_ok = g[same, 7] == o[same, 7]
+    # where the histories agree, the deposit voxels agree too: their number
+    # and the sum of their indices (an integer, exact in FP64)
+    v_ok = (g[same, 7] == o[same, 7]) & (g[same, 6] == o[same, 6])
     assert v_ok.mean() >= frac
 
 
@@ -86,5 +87,7 @@ def test_replay_full_size_patient_pencil(engine, orc):
     origin = (0.0, 128.5 * h[1], 250.5 * h[2])
     g, o = _replay(engine, orc, 14, prob, 20_000, 13, pencil=(origin, (1.0, 0.0, 0.0)))
     _check(g, o)
+    # long deposit lists occur: past the registers and LDS, into global memory
+    assert (o[:, 7] > 12).sum() >= 20
     led = engine.ledger(14)
     assert abs(ledger_balance(led)) < 1e-9
