@@ -83,13 +83,15 @@ typedef struct {
                                   deposit voxels, uniforms drawn, discarded energy)    */
 } nmd_run_opts;
 
-/* Ledger slots (MeV) and run-stats slots. */
+/* Ledger slots (MeV) and run-stats slots.  NMD_STAT_LIST_MERGES counts the
+ * histories that deposited in more organs than the per-history organ slots
+ * hold (three), whose organ scores were merged from the deposit list. */
 enum { NMD_LEDGER_EMITTED = 0, NMD_LEDGER_DEP_COMPTON, NMD_LEDGER_DEP_PE, NMD_LEDGER_DEP_CUTOFF,
        NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_N };
 enum { NMD_STAT_HISTORIES = 0, NMD_STAT_PHOTONS, NMD_STAT_STEPS, NMD_STAT_NULLS,
        NMD_STAT_COMPTON, NMD_STAT_PE, NMD_STAT_RAYLEIGH, NMD_STAT_DEPOSITS, NMD_STAT_MERGED,
        NMD_STAT_MAX_MERGED, NMD_STAT_ESCAPES, NMD_STAT_OVERFLOWS, NMD_STAT_CLAIMS,
-       NMD_STAT_RNG_BLOCKS, NMD_STAT_N };
+       NMD_STAT_RNG_BLOCKS, NMD_STAT_LIST_MERGES, NMD_STAT_N };
 
 /* ---- context ------------------------------------------------------------ */
 

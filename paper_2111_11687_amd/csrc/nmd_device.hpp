@@ -61,18 +61,27 @@ struct Stream {
   uint32_t pos;      // words buffered
   uint32_t n_drawn;  // uniforms handed out (debug records only)
 
-  __device__ __forceinline__ void init(uint32_t seed_lo, uint32_t seed_hi, unsigned long long hid,
-                                       uint32_t p) {
+  // The key and the phantom are the same for every lane of a wave: set them
+  // where the wave runs in step, so that they stay in scalar registers.
+  __device__ __forceinline__ void set_key(uint32_t seed_lo, uint32_t seed_hi) {
     k0 = seed_lo;
     k1 = seed_hi;
+  }
+  // Start the stream of history hid: its first two blocks.
+  __device__ __forceinline__ void start(unsigned long long hid) {
     h0 = (uint32_t)hid;
     h1 = (uint32_t)(hid >> 32);
-    pid = p;
     philox4x32_10<true>(0u, h0, h1, pid, k0, k1, b0, b1, b2, b3);
     philox4x32_10<true>(1u, h0, h1, pid, k0, k1, b4, b5, b6, b7);
     blk = 2;
     pos = 8;
     n_drawn = 0;
+  }
+  __device__ __forceinline__ void init(uint32_t seed_lo, uint32_t seed_hi, unsigned long long hid,
+                                       uint32_t p) {
+    set_key(seed_lo, seed_hi);
+    pid = p;
+    start(hid);
   }
   // Append the next block after the pos buffered words (pos <= 4).
   __device__ __forceinline__ void append() {

@@ -18,7 +18,8 @@ constexpr int kBlock = 256;             // transport workgroup size (4 waves)
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kMaxOrganSlots = 256;     // labels 0..255
 constexpr int kRecN = 10;               // per-history debug record width
-constexpr int kStatN = 14;
+constexpr int kStatN = 15;
+constexpr int kOrgCache = 3;              // organ score slots per history, in registers
 constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
 
 // Workgroups of the transport kernel the compiler must fit on one CU (it

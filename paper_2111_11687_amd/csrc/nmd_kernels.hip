@@ -139,6 +139,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   // the global positions go four at a time: a group never passes kDepCap,
   // so no bit index of a 64-bit position mask reaches 64
   static_assert(kDepCap <= 64 && (kDepCap - kTier) % 4 == 0, "deposit list tiers");
+  // a history with more organs than slots has more deposit voxels than list
+  // registers; three slots and the overflow bit fit the 32-bit id word
+  static_assert(kOrgCache >= kRegDep && kOrgCache <= 3, "organ slots");
+  static_assert(kStatN == NMD_STAT_N && kStatN <= 16, "run counters");
 
   for (int i = tid; i < P.n_pal; i += kBlock) {
     const float4 q = P.palette[i];
@@ -151,6 +155,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   __syncthreads();
 
   Stream<kDebug> st;
+  st.set_key(P.seed_lo, P.seed_hi);
+  st.pid = 0u;
 
   // lane state: which phase the lane waits for
   constexpr uint32_t kIdle = 0, kFlight = 1, kInteract = 2, kPhotonEnd = 3;
@@ -159,7 +165,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   int ev_t = 0;                 // 1 Compton, 2 photoelectric, 3 Rayleigh
   float px = 0, py = 0, pz = 0, ux = 0, uy = 0, uz = 0, E = 0;
   uint32_t photon = 0, n_real = 0, cnt = 0, psteps = 0;
-  uint32_t h_steps = 0, h_nulls = 0, h_cr = 0, h_pe_esc = 0;  // per-history counts
+  // per-history counts, kept per lane for the debug records; otherwise each
+  // pass adds its steps and events (ballot popcounts) to the wave's LDS
+  // counters, from lane 0 while the whole wave runs in step
+  uint32_t h_steps = 0, h_nulls = 0, h_cr = 0, h_pe_esc = 0;
   EnergyParams ep = {};
   // first kRegDep distinct deposit voxels of the history, in registers
   uint32_t rv[kRegDep], rr[kRegDep];
@@ -170,6 +179,13 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     rr[i] = 0u;
     re[i] = 0.0;
   }
+  // the history's organ scores q_o so far: up to kOrgCache organs, their
+  // ids packed eight bits each in oc_id; bit 31 is set once the history
+  // touches more organs, whose scores are then merged from the deposit list
+  uint32_t oc_id = 0u;
+  double oc_s[kOrgCache];
+#pragma unroll
+  for (int k = 0; k < kOrgCache; ++k) oc_s[k] = 0.0;
   unsigned long long run_rel = 0;
   double h_esc = 0, h_disc = 0;  // debug records only
 
@@ -233,7 +249,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
 
   auto start_history = [&](unsigned long long rel) {
     run_rel = rel;
-    st.init(P.seed_lo, P.seed_hi, hid0 + rel, D->pid);
+    st.start(hid0 + rel);
     float o0, o1, o2, d0, d1, d2;
     if (P.source_kind == 1) {
       o0 = P.po[0];
@@ -325,30 +341,28 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       }
     }
     if (d->n_org > 0) {
-      // the list registers turn into (organ, score) pairs
+      if (!(oc_id >> 31)) {
 #pragma unroll
-      for (int i = 0; i < kRegDep; ++i) {
-        const uint32_t oi = (uint32_t)i < cnt ? rr[i] >> 8 : 0u;
-        re[i] = oi ? re[i] * wl.w[oi] * s_irho[rr[i] & 0xFFu] : 0.0;
-        rr[i] = oi;
-      }
-      if (cnt <= (uint32_t)kRegDep) {
-#pragma unroll
-        for (int i = 0; i < kRegDep; ++i) {
-          bool first = rr[i] != 0;
-#pragma unroll
-          for (int k = 0; k < i; ++k) first = first && rr[k] != rr[i];
-          if (first) {
-            double s = re[i];
-#pragma unroll
-            for (int j = i + 1; j < kRegDep; ++j) s += rr[j] == rr[i] ? re[j] : 0.0;
-            atomicAdd(&wl.org[rr[i]].x, s);
-            atomicAdd(&wl.org[rr[i]].y, s * s);
+        for (int k = 0; k < kOrgCache; ++k) {
+          const uint32_t ok = (oc_id >> (8 * k)) & 0xFFu;
+          if (ok) {
+            atomicAdd(&wl.org[ok].x, oc_s[k]);
+            atomicAdd(&wl.org[ok].y, oc_s[k] * oc_s[k]);
           }
         }
       } else {
-        // long history: one scan of the list per distinct organ, each
-        // summing that organ's scores in list order
+        // more organs than slots, so more voxels than list registers: merge
+        // the organ scores over the whole list, whose registers turn into
+        // (organ, score) pairs first
+        atomicAdd(&wa.stat[14], 1ull);
+#pragma unroll
+        for (int i = 0; i < kRegDep; ++i) {
+          const uint32_t oi = rr[i] >> 8;
+          re[i] = oi ? re[i] * wl.w[oi] * s_irho[rr[i] & 0xFFu] : 0.0;
+          rr[i] = oi;
+        }
+        // one scan of the list per distinct organ, each summing that
+        // organ's scores in list order
         unsigned long long rem = 0ull;  // bit p: position p still to merge
 #pragma unroll
         for (int i = 0; i < kRegDep; ++i) rem |= rr[i] ? 1ull << i : 0ull;
@@ -413,6 +427,9 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         }
       }
     }
+    oc_id = 0u;
+#pragma unroll
+    for (int k = 0; k < kOrgCache; ++k) oc_s[k] = 0.0;
     atomicAdd(&wa.stat[8], (unsigned long long)cnt);
     atomicMax(&wa.stat[9], (unsigned long long)cnt);
     if (kDebug && final_flush) {
@@ -436,7 +453,33 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   // voxels (a shift register, so no entry is addressed by a run-time
   // index); the oldest one moves on to the next list position, which is in
   // LDS for the next kLdsDep positions and in global memory after them.
+  // Add the score e c / (m_v N_o) of a deposit in organ o to the history's
+  // organ slots: q_o sums these over the history's deposits in o.
+  auto organ_add = [&](uint32_t r16, double e) {
+    const uint32_t o = r16 >> 8;
+    if (o == 0u || (oc_id >> 31)) return;
+    const double sc = e * wl.w[o] * s_irho[r16 & 0xFFu];
+    bool hit = false;
+#pragma unroll
+    for (int k = 0; k < kOrgCache; ++k) {
+      const bool m = ((oc_id >> (8 * k)) & 0xFFu) == o;
+      oc_s[k] += m ? sc : 0.0;
+      hit = hit || m;
+    }
+    if (hit) return;
+    bool put = false;
+#pragma unroll
+    for (int k = 0; k < kOrgCache; ++k) {
+      const bool f = !put && ((oc_id >> (8 * k)) & 0xFFu) == 0u;
+      oc_s[k] = f ? sc : oc_s[k];
+      oc_id |= f ? o << (8 * k) : 0u;
+      put = put || f;
+    }
+    if (!put) oc_id |= 0x80000000u;
+  };
+
   auto deposit = [&](uint32_t v, uint32_t r16, double e) {
+    organ_add(r16, e);
     bool found = false;
 #pragma unroll
     for (int i = 0; i < kRegDep; ++i) {
@@ -512,6 +555,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         flush_wave();
         wp = pend_p;
         D = (CDesc *)(P.desc + P.slot[wp].id);
+        st.pid = D->pid;
         hid0 = *G(D->n_done);  // histories already run on this phantom
         cur_next = pend_next;
         cur_end = pend_end;
@@ -573,6 +617,16 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     const bool go_end = n_end && (n_end >= P.phase_min || n_end >= n_fly);
     if (go_int && (!go_end || n_int >= n_end)) {
       // ---- interactions at the collision points found by the flights
+      if (!kDebug) {
+        const uint32_t c1 = __popcll(__ballot(state == kInteract && ev_t == 1));
+        const uint32_t c2 = __popcll(__ballot(state == kInteract && ev_t == 2));
+        const uint32_t c3 = __popcll(__ballot(state == kInteract && ev_t == 3));
+        if (lane == 0) {
+          atomicAdd(&wa.stat[4], (unsigned long long)c1);
+          atomicAdd(&wa.stat[5], (unsigned long long)c2);
+          atomicAdd(&wa.stat[6], (unsigned long long)c3);
+        }
+      }
       if (state == kInteract) {
         ++n_real;
         // the first Klein-Nishina attempt and the azimuth (or the Rayleigh
@@ -581,7 +635,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         bool pdone = false;
         double dep = -1.0;  // energy left in voxel ev_v by this event
         if (ev_t == 1) {
-          ++h_cr;
+          if (kDebug) ++h_cr;
           float cost;
           const float eps = klein_nishina(st, E * (float)(1.0 / kMeC2), cost);
           const float uphi = st.uniform();
@@ -600,12 +654,12 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
             ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
           }
         } else if (ev_t == 2) {
-          ++h_pe_esc;
+          if (kDebug) ++h_pe_esc;
           dep = (double)E;
           atomicAdd(&wa.ledger[2], dep);
           pdone = true;
         } else {
-          h_cr += 0x10000u;
+          if (kDebug) h_cr += 0x10000u;
           const float cost = thomson(st.uniform());
           const float uphi = st.uniform();
           rotate(ux, uy, uz, cost, uphi);
@@ -633,12 +687,14 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         } else {
           atomicAdd(&wa.stat[0], 1ull);
           atomicAdd(&wa.stat[1], (unsigned long long)P.nph);
-          atomicAdd(&wa.stat[2], (unsigned long long)h_steps);
-          atomicAdd(&wa.stat[3], (unsigned long long)h_nulls);
-          atomicAdd(&wa.stat[4], (unsigned long long)(h_cr & 0xFFFFu));
-          atomicAdd(&wa.stat[5], (unsigned long long)(h_pe_esc & 0xFFFFu));
-          atomicAdd(&wa.stat[6], (unsigned long long)(h_cr >> 16));
-          atomicAdd(&wa.stat[10], (unsigned long long)(h_pe_esc >> 16));
+          if (kDebug) {
+            atomicAdd(&wa.stat[2], (unsigned long long)h_steps);
+            atomicAdd(&wa.stat[3], (unsigned long long)h_nulls);
+            atomicAdd(&wa.stat[4], (unsigned long long)(h_cr & 0xFFFFu));
+            atomicAdd(&wa.stat[5], (unsigned long long)(h_pe_esc & 0xFFFFu));
+            atomicAdd(&wa.stat[6], (unsigned long long)(h_cr >> 16));
+            atomicAdd(&wa.stat[10], (unsigned long long)(h_pe_esc >> 16));
+          }
           atomicAdd(&wa.stat[13], (unsigned long long)st.blk);
           flush_list(true);
           state = kIdle;
@@ -649,8 +705,9 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     }
     if (n_fly) {
       // ---- one Woodcock step per flying photon
+      uint32_t fk = 0u;  // how this lane's step ended: 1 null collision, 2 escape
       if (state == kFlight) {
-        ++h_steps;
+        if (kDebug) ++h_steps;
         st.reserve2();  // the step's two draws, refilled for all flying lanes at once
         const float s = -fast_log2(st.take_uniform()) * ep.inv_mu_ln2;
         px += s * ux;
@@ -661,7 +718,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         if (!(fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
               fz < D->fnz)) {
           atomicAdd(&wa.ledger[4], (double)E);
-          h_pe_esc += 0x10000u;
+          if (kDebug) h_pe_esc += 0x10000u;
+          fk = 2u;
           if (kDebug) h_esc += E;
           state = kPhotonEnd;
         } else if (++psteps > kMaxPhotonSteps) {
@@ -681,13 +739,23 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
           int ev = t < mc ? 1 : (t < mc + mpe ? 2 : (t < mc + mpe + mr ? 3 : 0));
           if (ev && !((P.mask >> (ev - 1)) & 1u)) ev = 0;
           if (ev == 0) {
-            ++h_nulls;
+            if (kDebug) ++h_nulls;
+            fk = 1u;
           } else {
             ev_t = ev;
             ev_v = v;
             ev_r = r16;
             state = kInteract;
           }
+        }
+      }
+      if (!kDebug) {
+        const uint32_t c1 = __popcll(__ballot(fk == 1u));
+        const uint32_t c2 = __popcll(__ballot(fk == 2u));
+        if (lane == 0) {
+          atomicAdd(&wa.stat[2], (unsigned long long)n_fly);
+          atomicAdd(&wa.stat[3], (unsigned long long)c1);
+          atomicAdd(&wa.stat[10], (unsigned long long)c2);
         }
       }
       continue;

@@ -123,6 +123,8 @@ def test_eq2_two_ways_on_device(engine, full):
         prob = P.patient_phantom(shape=(80, 64, 64), voxel_mm=(8.0, 8.0, 12.0), seed=9)
     engine.set_problem(21, prob)
     engine.run(21, 2 * 10 ** 6, 5)
+    if full:  # histories over more organs than the slots hold merge from the list
+        assert engine.stats(21)["list_merges"] > 1000
     r2, _, _ = engine.organs(21)
     rs = B.nmd_get_organ_score(engine.ctx, 21, prob.n_organs)
     nz = r2 > 0
