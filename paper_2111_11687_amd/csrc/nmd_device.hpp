@@ -155,29 +155,34 @@ __device__ __forceinline__ void marsaglia(S &st, float &dx, float &dy, float &dz
 // composition-rejection: the eps density (1/eps + eps) g(eps) on [eps0, 1]
 // is split into the exactly sampled 1/eps and eps parts, weighted by
 // ln(1/eps0) and (1 - eps0^2)/2, and thinned by g = 1 - eps sin^2/(1+eps^2).
+// One attempt draws three uniforms and returns whether it is accepted,
+// with eps and cos(theta) of the attempt.
 template <class S>
-__device__ __forceinline__ float klein_nishina(S &st, float k, float &cost) {
+__device__ __forceinline__ bool klein_nishina_try(S &st, float k, float &eps, float &cost) {
   const float a = 1.0f + 2.0f * k;
   const float eps0 = 1.0f / a;
   const float e02 = eps0 * eps0;
   const float a1 = fast_log2(a) * 0.69314718055994531f;  // ln(1 + 2k)
   const float a2 = 0.5f * (1.0f - e02);
   const float inv_k = 1.0f / k;
-  float eps, t;
-  for (;;) {
-    const float r1 = st.uniform();
-    const float r2 = st.uniform();
-    const float r3 = st.uniform();
-    if (r1 * (a1 + a2) < a1)
-      eps = fast_exp2(-a1 * r2 * 1.4426950408889634f);
-    else
-      eps = __builtin_sqrtf(e02 + (1.0f - e02) * r2);
-    t = (1.0f - eps) * inv_k / eps;
-    const float sin2 = t * (2.0f - t);
-    const float g = 1.0f - eps * sin2 / (1.0f + eps * eps);
-    if (r3 < g) break;
-  }
+  const float r1 = st.uniform();
+  const float r2 = st.uniform();
+  const float r3 = st.uniform();
+  if (r1 * (a1 + a2) < a1)
+    eps = fast_exp2(-a1 * r2 * 1.4426950408889634f);
+  else
+    eps = __builtin_sqrtf(e02 + (1.0f - e02) * r2);
+  const float t = (1.0f - eps) * inv_k / eps;
+  const float sin2 = t * (2.0f - t);
+  const float g = 1.0f - eps * sin2 / (1.0f + eps * eps);
   cost = 1.0f - t;
+  return r3 < g;
+}
+template <class S>
+__device__ __forceinline__ float klein_nishina(S &st, float k, float &cost) {
+  float eps;
+  while (!klein_nishina_try(st, k, eps, cost)) {
+  }
   return eps;
 }
 

@@ -617,63 +617,68 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     const bool go_end = n_end && (n_end >= P.phase_min || n_end >= n_fly);
     if (go_int && (!go_end || n_int >= n_end)) {
       // ---- interactions at the collision points found by the flights
+      uint32_t ek = 0u;  // the event this lane completed: 1 Compton, 2 photoelectric, 3 Rayleigh
+      if (state == kInteract) {
+        // the draws of one Klein-Nishina attempt and the azimuth (or the
+        // Rayleigh pair): generated here for all interacting lanes at once
+        if (ev_t != 2) st.reserve4();
+        // a rejected Klein-Nishina attempt leaves the lane waiting for the
+        // next interaction pass, so no lane holds the wave through retries
+        float eps = 1.0f, cost = 1.0f;
+        if (ev_t != 1 || klein_nishina_try(st, E * (float)(1.0 / kMeC2), eps, cost)) {
+          ++n_real;
+          ek = (uint32_t)ev_t;
+          bool pdone = false;
+          double dep = -1.0;  // energy left in voxel ev_v by this event
+          if (ev_t == 1) {
+            if (kDebug) ++h_cr;
+            const float uphi = st.uniform();
+            const float e1 = eps * E;
+            dep = (double)E - (double)e1;  // exact in FP64
+            atomicAdd(&wa.ledger[1], dep);
+            rotate(ux, uy, uz, cost, uphi);
+            E = e1;
+            if (E < P.cutoff) {
+              // the cutoff energy stays in the same voxel: T + E' = E
+              atomicAdd(&wa.ledger[3], (double)E);
+              atomicAdd(&wa.stat[7], 1ull);
+              dep += (double)E;
+              pdone = true;
+            } else {
+              ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+            }
+          } else if (ev_t == 2) {
+            if (kDebug) ++h_pe_esc;
+            dep = (double)E;
+            atomicAdd(&wa.ledger[2], dep);
+            pdone = true;
+          } else {
+            if (kDebug) h_cr += 0x10000u;
+            const float ct = thomson(st.uniform());
+            const float uphi = st.uniform();
+            rotate(ux, uy, uz, ct, uphi);
+          }
+          if (dep >= 0.0) {
+            atomicAdd(&wa.stat[7], 1ull);
+            deposit(ev_v, ev_r, dep);
+          }
+          if (!pdone && P.max_real && n_real >= P.max_real) {
+            atomicAdd(&wa.ledger[5], (double)E);
+            if (kDebug) h_disc += E;
+            pdone = true;
+          }
+          state = pdone ? kPhotonEnd : kFlight;
+        }
+      }
       if (!kDebug) {
-        const uint32_t c1 = __popcll(__ballot(state == kInteract && ev_t == 1));
-        const uint32_t c2 = __popcll(__ballot(state == kInteract && ev_t == 2));
-        const uint32_t c3 = __popcll(__ballot(state == kInteract && ev_t == 3));
+        const uint32_t c1 = __popcll(__ballot(ek == 1u));
+        const uint32_t c2 = __popcll(__ballot(ek == 2u));
+        const uint32_t c3 = __popcll(__ballot(ek == 3u));
         if (lane == 0) {
           atomicAdd(&wa.stat[4], (unsigned long long)c1);
           atomicAdd(&wa.stat[5], (unsigned long long)c2);
           atomicAdd(&wa.stat[6], (unsigned long long)c3);
         }
-      }
-      if (state == kInteract) {
-        ++n_real;
-        // the first Klein-Nishina attempt and the azimuth (or the Rayleigh
-        // pair): generated here for all interacting lanes at once
-        if (ev_t != 2) st.reserve4();
-        bool pdone = false;
-        double dep = -1.0;  // energy left in voxel ev_v by this event
-        if (ev_t == 1) {
-          if (kDebug) ++h_cr;
-          float cost;
-          const float eps = klein_nishina(st, E * (float)(1.0 / kMeC2), cost);
-          const float uphi = st.uniform();
-          const float e1 = eps * E;
-          dep = (double)E - (double)e1;  // exact in FP64
-          atomicAdd(&wa.ledger[1], dep);
-          rotate(ux, uy, uz, cost, uphi);
-          E = e1;
-          if (E < P.cutoff) {
-            // the cutoff energy stays in the same voxel: T + E' = E
-            atomicAdd(&wa.ledger[3], (double)E);
-            atomicAdd(&wa.stat[7], 1ull);
-            dep += (double)E;
-            pdone = true;
-          } else {
-            ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
-          }
-        } else if (ev_t == 2) {
-          if (kDebug) ++h_pe_esc;
-          dep = (double)E;
-          atomicAdd(&wa.ledger[2], dep);
-          pdone = true;
-        } else {
-          if (kDebug) h_cr += 0x10000u;
-          const float cost = thomson(st.uniform());
-          const float uphi = st.uniform();
-          rotate(ux, uy, uz, cost, uphi);
-        }
-        if (dep >= 0.0) {
-          atomicAdd(&wa.stat[7], 1ull);
-          deposit(ev_v, ev_r, dep);
-        }
-        if (!pdone && P.max_real && n_real >= P.max_real) {
-          atomicAdd(&wa.ledger[5], (double)E);
-          if (kDebug) h_disc += E;
-          pdone = true;
-        }
-        state = pdone ? kPhotonEnd : kFlight;
       }
       continue;
     }
