@@ -19,6 +19,7 @@ constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kMaxOrganSlots = 256;     // labels 0..255
 constexpr int kRecN = 10;               // per-history debug record width
 constexpr int kStatN = 15;
+constexpr int kFlySteps = 2;              // Woodcock steps per flight pass and photon
 constexpr int kOrgCache = 3;              // organ score slots per history, in registers
 constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
 

@@ -143,6 +143,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   // registers; three slots and the overflow bit fit the 32-bit id word
   static_assert(kOrgCache >= kRegDep && kOrgCache <= 3, "organ slots");
   static_assert(kStatN == NMD_STAT_N && kStatN <= 16, "run counters");
+  // a pass's steps draw at most two words each, all buffered by reserve4
+  static_assert(kFlySteps >= 1 && kFlySteps <= 2, "steps per flight pass");
 
   for (int i = tid; i < P.n_pal; i += kBlock) {
     const float4 q = P.palette[i];
@@ -709,58 +711,67 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       continue;
     }
     if (n_fly) {
-      // ---- one Woodcock step per flying photon
-      uint32_t fk = 0u;  // how this lane's step ended: 1 null collision, 2 escape
+      // ---- Woodcock steps: a flying photon takes up to kFlySteps steps per
+      // pass, the next one only after a null collision, so the pass's fixed
+      // costs (phase choice, generator refill) are shared by more steps
+      uint32_t ns = 0u, nn = 0u, ne = 0u;  // this lane's steps, null collisions, escapes
       if (state == kFlight) {
-        if (kDebug) ++h_steps;
-        st.reserve2();  // the step's two draws, refilled for all flying lanes at once
-        const float s = -fast_log2(st.take_uniform()) * ep.inv_mu_ln2;
-        px += s * ux;
-        py += s * uy;
-        pz += s * uz;
-        const float fx = px * D->inv_dx, fy = py * D->inv_dy, fz = pz * D->inv_dz;
-        // written so that a NaN coordinate counts as outside
-        if (!(fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
-              fz < D->fnz)) {
-          atomicAdd(&wa.ledger[4], (double)E);
-          if (kDebug) h_pe_esc += 0x10000u;
-          fk = 2u;
-          if (kDebug) h_esc += E;
-          state = kPhotonEnd;
-        } else if (++psteps > kMaxPhotonSteps) {
-          // unreachable for valid input; bounds the loop for any input
-          atomicAdd(&wa.ledger[5], (double)E);
-          if (kDebug) h_disc += E;
-          state = kPhotonEnd;
-        } else {
-          const uint32_t v =
-              (uint32_t)fx + (uint32_t)D->nx * ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz);
-          const uint32_t r16 = G(D->rec)[v];
-          const float4 pal = s_pal[r16 & 0xFFu];
-          const float mc = pal.x * ep.sig;
-          const float mpe = pal.y * ep.gpe;
-          const float mr = pal.z * ep.gr;
-          const float t = st.take_uniform() * ep.mu_hat;
-          int ev = t < mc ? 1 : (t < mc + mpe ? 2 : (t < mc + mpe + mr ? 3 : 0));
-          if (ev && !((P.mask >> (ev - 1)) & 1u)) ev = 0;
-          if (ev == 0) {
-            if (kDebug) ++h_nulls;
-            fk = 1u;
+        st.reserve4();  // two steps' draws, refilled for all flying lanes at once
+#pragma unroll
+        for (int k = 0; k < kFlySteps; ++k) {
+          if (state != kFlight) break;
+          if (kDebug) ++h_steps;
+          ++ns;
+          const float s = -fast_log2(st.take_uniform()) * ep.inv_mu_ln2;
+          px += s * ux;
+          py += s * uy;
+          pz += s * uz;
+          const float fx = px * D->inv_dx, fy = py * D->inv_dy, fz = pz * D->inv_dz;
+          // written so that a NaN coordinate counts as outside
+          if (!(fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
+                fz < D->fnz)) {
+            atomicAdd(&wa.ledger[4], (double)E);
+            if (kDebug) h_pe_esc += 0x10000u;
+            ++ne;
+            if (kDebug) h_esc += E;
+            state = kPhotonEnd;
+          } else if (++psteps > kMaxPhotonSteps) {
+            // unreachable for valid input; bounds the loop for any input
+            atomicAdd(&wa.ledger[5], (double)E);
+            if (kDebug) h_disc += E;
+            state = kPhotonEnd;
           } else {
-            ev_t = ev;
-            ev_v = v;
-            ev_r = r16;
-            state = kInteract;
+            const uint32_t v =
+                (uint32_t)fx + (uint32_t)D->nx * ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz);
+            const uint32_t r16 = G(D->rec)[v];
+            const float4 pal = s_pal[r16 & 0xFFu];
+            const float mc = pal.x * ep.sig;
+            const float mpe = pal.y * ep.gpe;
+            const float mr = pal.z * ep.gr;
+            const float t = st.take_uniform() * ep.mu_hat;
+            int ev = t < mc ? 1 : (t < mc + mpe ? 2 : (t < mc + mpe + mr ? 3 : 0));
+            if (ev && !((P.mask >> (ev - 1)) & 1u)) ev = 0;
+            if (ev == 0) {
+              if (kDebug) ++h_nulls;
+              ++nn;
+            } else {
+              ev_t = ev;
+              ev_v = v;
+              ev_r = r16;
+              state = kInteract;
+            }
           }
         }
       }
       if (!kDebug) {
-        const uint32_t c1 = __popcll(__ballot(fk == 1u));
-        const uint32_t c2 = __popcll(__ballot(fk == 2u));
+        // per-lane counts are at most 2: count them by their binary digits
+        const uint32_t c_s = __popcll(__ballot(ns & 1u)) + 2u * __popcll(__ballot(ns & 2u));
+        const uint32_t c_n = __popcll(__ballot(nn & 1u)) + 2u * __popcll(__ballot(nn & 2u));
+        const uint32_t c_e = __popcll(__ballot(ne != 0u));
         if (lane == 0) {
-          atomicAdd(&wa.stat[2], (unsigned long long)n_fly);
-          atomicAdd(&wa.stat[3], (unsigned long long)c1);
-          atomicAdd(&wa.stat[10], (unsigned long long)c2);
+          atomicAdd(&wa.stat[2], (unsigned long long)c_s);
+          atomicAdd(&wa.stat[3], (unsigned long long)c_n);
+          atomicAdd(&wa.stat[10], (unsigned long long)c_e);
         }
       }
       continue;
