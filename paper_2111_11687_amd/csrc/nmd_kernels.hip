@@ -74,6 +74,7 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
 struct WaveAcc {
   double ledger[6];
   unsigned long long stat[kStatN];
+  float ep0[5];  // energy_params at the emission energy, for the wave's phantom
 };
 
 // Per-wave part of the dynamic LDS: organ score accumulators, majorant table
@@ -233,6 +234,16 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       wl.org[i] = make_double2(0.0, 0.0);
     }
     wave_lds_sync();
+    // every photon starts at the emission energy: its factors, once
+    const EnergyParams e0 = energy_params(kE0, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+    if (lane == 0) {
+      wa.ep0[0] = e0.sig;
+      wa.ep0[1] = e0.gpe;
+      wa.ep0[2] = e0.gr;
+      wa.ep0[3] = e0.mu_hat;
+      wa.ep0[4] = e0.inv_mu_ln2;
+    }
+    wave_lds_sync();
   };
 
   auto start_photon = [&]() {
@@ -246,7 +257,11 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     E = kE0;
     n_real = 0;
     psteps = 0;
-    ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+    ep.sig = wa.ep0[0];
+    ep.gpe = wa.ep0[1];
+    ep.gr = wa.ep0[2];
+    ep.mu_hat = wa.ep0[3];
+    ep.inv_mu_ln2 = wa.ep0[4];
   };
 
   auto start_history = [&](unsigned long long rel) {
@@ -670,6 +685,12 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
             pdone = true;
           }
           state = pdone ? kPhotonEnd : kFlight;
+          if (pdone && photon + 1 < P.nph) {
+            // the next photon of the pair leaves at once: it draws nothing
+            ++photon;
+            start_photon();
+            state = kFlight;
+          }
         }
       }
       if (!kDebug) {
@@ -685,7 +706,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       continue;
     }
     if (go_end) {
-      // ---- photon ends: start the second photon, or score the history
+      // ---- history ends: score the history.  A photon that ends with a
+      // photon of its pair still to go starts that one where it ends (in the
+      // flight or interaction pass), so lanes wait here only for the history
+      // end; the branch for a next photon stays as the general case.
       if (state == kPhotonEnd) {
         if (photon + 1 < P.nph) {
           ++photon;
@@ -762,6 +786,12 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
             }
           }
         }
+      }
+      if (state == kPhotonEnd && photon + 1 < P.nph) {
+        // the next photon of the pair leaves at once: it draws nothing
+        ++photon;
+        start_photon();
+        state = kFlight;
       }
       if (!kDebug) {
         // per-lane counts are at most 2: count them by their binary digits
