@@ -41,7 +41,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # Bytes moved beyond L2 per decay by the transport kernel on the patient
 # phantom: FETCH_SIZE x 2 + WRITE_SIZE of rocprofv3 --pmc runs, scaled
 # against a profiled 256 MiB copy (profiles/transport_patient256x256x320_counters.md).
-TRANSPORT_TRAFFIC_BYTES_PER_DECAY = 1771.0
+TRANSPORT_TRAFFIC_BYTES_PER_DECAY = 1769.0
 
 
 def valu_ops(stats):
