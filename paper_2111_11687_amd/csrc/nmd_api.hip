@@ -95,7 +95,6 @@ struct nmd_ctx {
   uint64_t next_gen = 1;
   int cu_count = 0;
   float l2emin = 0, inv_dl2 = 0;
-  uint32_t phase_min = 32;  // tuning: NMD_PHASE_MIN
   std::map<int, Phantom> ph;
   DevBuf nn_scratch;  // workspace of the denoiser's backward-weight partials
   bool poisoned = false;
@@ -401,7 +400,6 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
   rp.l2emin = c->l2emin;
   rp.inv_dl2 = c->inv_dl2;
   rp.n_slots = n_slots;
-  rp.phase_min = c->phase_min;
   rp.n_lanes = lanes;
   rp.hist_rec = o.history_records;
   return NMD_OK;
@@ -488,10 +486,6 @@ nmd_status nmd_create(nmd_ctx **out, int device, void *stream) {
   for (char &ch : c->arch)
     if (ch == ' ' || ch == '|') ch = '_';
   load_tune_cache(c);
-  if (const char *e = std::getenv("NMD_PHASE_MIN")) {
-    const long v = std::strtol(e, nullptr, 10);
-    if (v >= 1 && v <= 64) c->phase_min = (uint32_t)v;
-  }
   c->l2emin = (float)std::log2(kEGridMin);
   c->inv_dl2 = (float)((kNGrid - 1) / std::log2(kEGridRatio));
   std::vector<float> kn(kNGrid);

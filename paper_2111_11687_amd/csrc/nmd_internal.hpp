@@ -19,6 +19,9 @@ constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kMaxOrganSlots = 256;     // labels 0..255
 constexpr int kRecN = 10;               // per-history debug record width
 constexpr int kStatN = 15;
+// lanes that wait before their phase runs (unless they outnumber the
+// flights): interactions, and history ends (the costlier pass)
+constexpr uint32_t kPhaseMinInt = 24, kPhaseMinEnd = 40;
 constexpr int kFlySteps = 2;              // Woodcock steps per flight pass and photon
 constexpr int kOrgCache = 3;              // organ score slots per history, in registers
 constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
@@ -95,7 +98,6 @@ struct RunParams {
   double *dep_e;             //   energy
   uint32_t *dep_r;           //   voxel record
   int32_t n_slots;           // largest n_org + 1 of the launch's phantoms
-  uint32_t phase_min;        // lanes that must wait before a phase runs
   uint32_t n_lanes;
   double *hist_rec;          // debug [n_hist][kRecN] or nullptr
   RunSlot slot[kMaxPhantoms];

@@ -629,9 +629,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     const uint32_t n_fly = __popcll(__ballot(state == kFlight));
     const uint32_t n_int = __popcll(__ballot(state == kInteract));
     const uint32_t n_end = __popcll(__ballot(state == kPhotonEnd));
-    // a waiting phase runs once it has phase_min lanes or outnumbers the flights
-    const bool go_int = n_int && (n_int >= P.phase_min || n_int >= n_fly);
-    const bool go_end = n_end && (n_end >= P.phase_min || n_end >= n_fly);
+    // a waiting phase runs once it has its threshold of lanes or outnumbers
+    // the flights
+    const bool go_int = n_int && (n_int >= kPhaseMinInt || n_int >= n_fly);
+    const bool go_end = n_end && (n_end >= kPhaseMinEnd || n_end >= n_fly);
     if (go_int && (!go_end || n_int >= n_end)) {
       // ---- interactions at the collision points found by the flights
       uint32_t ek = 0u;  // the event this lane completed: 1 Compton, 2 photoelectric, 3 Rayleigh
