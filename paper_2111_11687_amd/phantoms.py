@@ -350,3 +350,62 @@ def batch_phantoms(n=64, first_seed=4000, n_decays=10 ** 7):
 def pencil_line(problem: Problem, axis_y_cm: float, axis_z_cm: float):
     """Origin on the x = 0 face and direction +x for a pencil beam at (y, z)."""
     return (0.0, axis_y_cm, axis_z_cm), (1.0, 0.0, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Synthetic CT images (inputs of the CT ingestion)
+# ---------------------------------------------------------------------------
+# A stand-in HU-to-density curve with material thresholds: the paper cites
+# Schneider et al. (2000) without giving its parameters.  The nodes put the
+# four phantom materials at air -1000, lung -740, soft tissue 0 and bone
+# +1100 HU.  Per material, densities are kept to a few levels (the engine
+# holds at most 256 distinct material-density pairs): 8 for air, 32 for
+# lung, 64 for soft tissue and 64 for bone, placed so that each nominal
+# density is a level centre.
+SYNTHETIC_CT_TABLE = dict(
+    hu=[-1000.0, -740.0, 0.0, 1100.0, 3000.0],
+    density=[0.0012, 0.26, 1.0, 1.85, 2.9],
+    threshold=[-950.0, -200.0, 300.0],
+    density_min=[0.0, 0.05, 0.7975, 1.0875],
+    density_width=[0.0024, 0.02, 0.005, 0.025],
+    levels=[8, 32, 64, 64],
+)
+# material order of the table: air, lung, soft tissue, bone
+CT_MATERIAL_NAMES = ("air", "lung", "soft_tissue", "bone")
+MATERIAL_HU = {"air": -1000.0, "lung": -740.0, "soft_tissue": 0.0, "water": 0.0, "bone": 1100.0}
+
+
+def render_ct(problem: Problem, factor=(2, 2, 1), pad_mm=(8.0, 8.0, 6.0), noise_hu=5.0,
+              seed=11):
+    """A synthetic CT of ``problem``: a grid ``factor`` times finer than the
+    phantom's (per axis x, y, z), extending ``pad_mm`` beyond it on each side,
+    with the nominal HU of each voxel's material plus Gaussian noise of
+    ``noise_hu``, and -1000 HU outside the phantom.  The material of a CT
+    voxel is that of the phantom voxel holding its centre.  Returns
+    ``(hu float32 [nz][ny][nx], ct_grid, phantom_grid)``; grids are dicts
+    ``n=(nx, ny, nz), spacing=(sx, sy, sz), origin=(ox, oy, oz)`` in mm, with
+    the phantom's outer corner at the origin."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = problem.shape
+    vm = problem.voxel_mm
+    ph_grid = dict(n=(nx, ny, nz), spacing=tuple(float(v) for v in vm), origin=(0.0, 0.0, 0.0))
+    sp = tuple(float(vm[a]) / factor[a] for a in range(3))
+    n = tuple(int(round((problem.shape[2 - a] * vm[a] + 2 * pad_mm[a]) / sp[a])) for a in range(3))
+    ct_grid = dict(n=n, spacing=sp, origin=tuple(-float(p) for p in pad_mm))
+    names = [None] * len(problem.materials)
+    for name, (z, za, _) in MATERIALS.items():
+        for i, (mz, mza) in enumerate(problem.materials):
+            if names[i] is None and (mz, mza) == (z, za):
+                names[i] = name
+    mat_hu = np.array([MATERIAL_HU[n_] for n_ in names], dtype=np.float32)
+    idx = []
+    for a in range(3):
+        c = ct_grid["origin"][a] + (np.arange(n[a]) + 0.5) * sp[a]
+        i = np.floor(c / vm[a]).astype(np.int64)
+        idx.append((i, (i >= 0) & (i < problem.shape[2 - a])))
+    (ix, okx), (iy, oky), (iz, okz) = idx
+    inside = okz[:, None, None] & oky[None, :, None] & okx[None, None, :]
+    m = problem.material[np.clip(iz, 0, nz - 1)][:, np.clip(iy, 0, ny - 1)][:, :, np.clip(ix, 0, nx - 1)]
+    hu = np.where(inside, mat_hu[m], np.float32(-1000.0)).astype(np.float32)
+    hu += rng.normal(0.0, noise_hu, size=hu.shape).astype(np.float32)
+    return hu, ct_grid, ph_grid
