@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--decays-per-step", type=int, default=10 ** 8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("patient", "batch64", "denoiser", "organ-time"),
+    ap.add_argument("--workload", choices=("patient", "batch64", "denoiser", "organ-time", "ingest"),
                     default="patient",
                     help="patient: the 256x256x320 phantom (the headline metric); batch64: 64 "
                          "uneven phantoms, 10^7 decays each per step, one graph-captured "
@@ -118,6 +118,8 @@ def main():
         return bench_batch(args)
     if args.workload == "denoiser":
         return bench_denoiser(args)
+    if args.workload == "ingest":
+        return bench_ingest(args)
     if args.workload == "organ-time":
         return bench_organ_time(args)
     prob = P.patient_phantom()
@@ -355,6 +357,123 @@ def bench_denoiser(args):
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_denoiser(min(args.cpu_seconds, 15.0))
+    eng.close()
+    print(json.dumps(res), flush=True)
+
+
+HBM_PEAK = 8.0e12  # bytes/s
+# HBM bytes of one ingest_kernel launch on the benchmark's CT: FETCH_SIZE x 2
+# + WRITE_SIZE of rocprofv3 --pmc runs scaled against a profiled 256 MiB copy
+# (profiles/ingest_ct512x512x438_to_patient256x256x320.md)
+INGEST_TRAFFIC_BYTES = (149434.6 * 2 + 102426.7) * 1024
+
+
+def cpu_baseline_ingest(hu, ct_grid, ph_grid, target_s):
+    """The ingestion oracle on slabs of 4 dose-grid planes."""
+    from oracle import ingest as I
+    from paper_2111_11687_amd import phantoms as P
+    nx, ny, nz = ph_grid["n"]
+    n, z, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < target_s:
+        sub = dict(n=(nx, ny, 4), spacing=ph_grid["spacing"],
+                   origin=(ph_grid["origin"][0], ph_grid["origin"][1],
+                           ph_grid["origin"][2] + ph_grid["spacing"][2] * z))
+        v = I.resample_linear(hu, ct_grid, sub, -1000.0)
+        I.ct_to_phantom(v.astype(np.float32), P.SYNTHETIC_CT_TABLE)
+        n += nx * ny * 4
+        z = (z + 4) % (nz - 3)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "dose-grid voxels/s", "cores": 1, "kind": "oracle",
+            "sample": "%d dose-grid voxels in slabs of 4 planes, %.1f s" % (n, dt)}
+
+
+def bench_ingest(args):
+    """CT ingestion (Sections 2.1, 2.2): a 512x512x438 CT of 1.333x1.333x2.5 mm
+    resampled onto the 256x256x320 patient grid of 2x2x3 mm and converted to
+    the density and material grids of the phantom, in one pass
+    (nmd_ct_ingest); the two-call path is timed beside it."""
+    import torch
+    from paper_2111_11687_amd import binding as B
+    from paper_2111_11687_amd import phantoms as P
+
+    prob = P.patient_phantom()
+    hu, ctg, phg = P.render_ct(prob, factor=(1.5, 1.5, 1.2), pad_mm=(256.0 / 3.0, 256.0 / 3.0, 67.5))
+    table = P.SYNTHETIC_CT_TABLE
+    eng = B.Engine(0)
+    src = torch.from_numpy(hu).cuda()
+    nx, ny, nz = phg["n"]
+    vol = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+    dens = torch.empty_like(vol)
+    mat = torch.empty((nz, ny, nx), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        B.nmd_ct_ingest(eng.ctx, src, ctg, phg, table, dens, mat)
+        if ev:
+            ev[1].record(stream)
+
+    def two_calls(ev):
+        ev[0].record(stream)
+        B.nmd_resample_linear(eng.ctx, src, ctg, phg, -1000.0, vol)
+        ev[1].record(stream)
+        B.nmd_ct_to_phantom(eng.ctx, vol, table, dens, mat)
+        ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(2)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for ev in evs:
+        step(ev)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    in_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ev2 = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
+    for ev in ev2:
+        two_calls(ev)
+    torch.cuda.synchronize()
+    rs_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev2]))
+    ct_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev2]))
+    n_dst = nx * ny * nz
+    # algorithmic bytes: each CT voxel that some interpolation cell uses, read
+    # once (the CT's field of view is wider than the dose grid's, so about
+    # half of it is), and the density (4 B) and material (1 B) of every
+    # dose-grid voxel written once.  The cells are separable: count per axis.
+    touched = 1
+    for ax in range(3):
+        i = np.arange(phg["n"][ax], dtype=np.float32)
+        p = np.float32(phg["origin"][ax]) + (i + np.float32(0.5)) * np.float32(phg["spacing"][ax])
+        u = (p - np.float32(ctg["origin"][ax])) / np.float32(ctg["spacing"][ax]) - np.float32(0.5)
+        n_s = ctg["n"][ax]
+        u = u[(u >= -0.5) & (u <= n_s - 0.5)]
+        i0 = np.minimum(np.floor(np.clip(u, 0, n_s - 1)).astype(np.int64), max(n_s - 2, 0))
+        touched *= len(np.union1d(i0, np.minimum(i0 + 1, n_s - 1)))
+    in_bytes = 4 * touched + 5 * n_dst
+    achieved = in_bytes / (in_ms * 1e-3)
+    res = {
+        "metric": "CT ingestion throughput (CT to dose-grid phantom)",
+        "value": args.steps * n_dst / dt, "unit": "dose-grid voxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "CT 512x512x438 of 1.333x1.333x2.5 mm (HU, rendered from the "
+                               "patient phantom with a wider field of view) to the 256x256x320 "
+                               "patient grid of 2x2x3 mm: trilinear resampling, then HU to "
+                               "density and material, in one pass",
+                   "ingest_ms": in_ms, "two_call_resample_ms": rs_ms,
+                   "two_call_convert_ms": ct_ms, "ct_voxels": int(hu.size),
+                   "ct_voxels_used": int(touched)},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": INGEST_TRAFFIC_BYTES, "traffic_unit": "bytes per launch (profiled)",
+                     "kernel": "ingest_kernel", "kernel_ms": in_ms,
+                     "algorithmic_bytes": in_bytes},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_ingest(hu, ctg, phg, min(args.cpu_seconds, 15.0))
     eng.close()
     print(json.dumps(res), flush=True)
 

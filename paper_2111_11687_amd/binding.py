@@ -54,13 +54,28 @@ NN_EXPORTS = ("nmd_conv3d_fwd", "nmd_conv3d_bwd_data", "nmd_conv3d_bwd_weight", 
               "nmd_nn_combine", "nmd_nn_prepare", "nmd_nn_head_loss", "nmd_nn_head_infer",
               "nmd_nn_adam", "nmd_nn_cast_weight", "nmd_organ_mean_map", "nmd_debug_mfma")
 
+INGEST_EXPORTS = ("nmd_resample_linear", "nmd_ct_to_phantom", "nmd_ct_ingest")
+
+
+class nmd_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("spacing_mm", ctypes.c_float * 3),
+                ("origin_mm", ctypes.c_float * 3)]
+
+
+class nmd_ct_table(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("hu", ctypes.c_float * 32),
+                ("density", ctypes.c_float * 32), ("n_materials", ctypes.c_int32),
+                ("hu_threshold", ctypes.c_float * 7), ("density_min", ctypes.c_float * 8),
+                ("density_width", ctypes.c_float * 8), ("levels", ctypes.c_int32 * 8)]
+
+
 EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_run_opts_default", "nmd_set_phantom", "nmd_set_activity", "nmd_run_histories",
            "nmd_reset_tallies", "nmd_get_dose", "nmd_get_organ_dose", "nmd_get_organ_score",
            "nmd_get_ledger", "nmd_get_run_stats", "nmd_get_tallies", "nmd_set_tallies",
            "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
            "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
-           "nmd_graph_launch", "nmd_graph_destroy") + NN_EXPORTS
+           "nmd_graph_launch", "nmd_graph_destroy") + NN_EXPORTS + INGEST_EXPORTS
 
 _lib = None
 
@@ -119,6 +134,11 @@ def load_library(path: str = LIB_PATH):
         "nmd_nn_cast_weight": [vp, vp, i32, i32, vp, vp],
         "nmd_organ_mean_map": [vp, i32, vp, i32, vp],
         "nmd_debug_mfma": [vp, vp, vp, vp],
+        "nmd_resample_linear": [vp, vp, ctypes.POINTER(nmd_grid), ctypes.POINTER(nmd_grid),
+                                ctypes.c_float, vp],
+        "nmd_ct_to_phantom": [vp, vp, ctypes.c_int64, ctypes.POINTER(nmd_ct_table), vp, vp],
+        "nmd_ct_ingest": [vp, vp, ctypes.POINTER(nmd_grid), ctypes.POINTER(nmd_grid),
+                          ctypes.POINTER(nmd_ct_table), vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -401,6 +421,53 @@ def nmd_organ_mean_map(ctx, phantom_id, dose_map, n_organs):
                                                   int(n_organs),
                                                   out.ctypes.data_as(ctypes.c_void_p)))
     return out
+
+
+def make_grid(g):
+    """nmd_grid from a dict n=(nx, ny, nz), spacing=(sx, sy, sz), origin=(ox, oy, oz) (mm)."""
+    out = nmd_grid()
+    for a in range(3):
+        out.n[a] = int(g["n"][a])
+        out.spacing_mm[a] = float(g["spacing"][a])
+        out.origin_mm[a] = float(g["origin"][a])
+    return out
+
+
+def make_ct_table(t):
+    """nmd_ct_table from a dict with hu, density, threshold, density_min,
+    density_width and levels."""
+    out = nmd_ct_table()
+    out.n_nodes = len(t["hu"])
+    for i, (h, d) in enumerate(zip(t["hu"], t["density"])):
+        out.hu[i] = float(h)
+        out.density[i] = float(d)
+    out.n_materials = len(t["levels"])
+    for i, h in enumerate(t["threshold"]):
+        out.hu_threshold[i] = float(h)
+    for i in range(out.n_materials):
+        out.density_min[i] = float(t["density_min"][i])
+        out.density_width[i] = float(t["density_width"][i])
+        out.levels[i] = int(t["levels"][i])
+    return out
+
+
+def nmd_resample_linear(ctx, src, src_grid, dst_grid, fill, dst):
+    _check(ctx, load_library().nmd_resample_linear(ctx, _dptr(src), ctypes.byref(make_grid(src_grid)),
+                                                   ctypes.byref(make_grid(dst_grid)), float(fill),
+                                                   _dptr(dst)))
+
+
+def nmd_ct_to_phantom(ctx, hu, table, density, material):
+    _check(ctx, load_library().nmd_ct_to_phantom(ctx, _dptr(hu), int(hu.numel()),
+                                                 ctypes.byref(make_ct_table(table)),
+                                                 _dptr(density), _dptr(material)))
+
+
+def nmd_ct_ingest(ctx, ct_hu, ct_grid, dose_grid, table, density, material):
+    _check(ctx, load_library().nmd_ct_ingest(ctx, _dptr(ct_hu), ctypes.byref(make_grid(ct_grid)),
+                                             ctypes.byref(make_grid(dose_grid)),
+                                             ctypes.byref(make_ct_table(table)), _dptr(density),
+                                             _dptr(material)))
 
 
 def nmd_debug_mfma(ctx, a, b, d):

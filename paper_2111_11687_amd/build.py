@@ -7,9 +7,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("nmd_kernels.hip", "nmd_api.hip", "nmd_nn.hip")]
+SOURCES = [os.path.join(CSRC, f)
+           for f in ("nmd_kernels.hip", "nmd_api.hip", "nmd_nn.hip", "nmd_ingest.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("nmd_internal.hpp", "nmd_device.hpp")] + [
-    os.path.join(HERE, "..", "include", f) for f in ("nmdose.h", "nmdose_nn.h")]
+    os.path.join(HERE, "..", "include", f) for f in ("nmdose.h", "nmdose_nn.h", "nmdose_ingest.h")]
 LIB = os.path.join(HERE, "libnmdose.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1,0 +1,179 @@
+"""CT ingestion on the device (nmd_resample_linear, nmd_ct_to_phantom)
+against the oracle (oracle/ingest.py).
+
+Bars: inside/outside decisions and fill values identical; interpolated
+values within float32 rounding of the oracle's float64 sums of the same
+float32 weights and samples (|d| <= 2^-21 max|src| + 2^-22 |ref|: four
+lerps of float32 rounding); HU conversion bit-exact (every step is the same
+float32 operation on both sides).  Sizes are ragged and span many
+workgroups; the full-size case is the benchmark's CT-to-patient-grid shape,
+checked on slabs the oracle recomputes."""
+import numpy as np
+import pytest
+
+from oracle import ingest as I
+from paper_2111_11687_amd import binding as B
+from paper_2111_11687_amd import phantoms as P
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+
+
+def grid(n, spacing, origin):
+    return dict(n=tuple(int(x) for x in n), spacing=tuple(float(x) for x in spacing),
+                origin=tuple(float(x) for x in origin))
+
+
+def gpu_resample(engine, src, sg, dg, fill):
+    t = engine.torch
+    s = t.from_numpy(np.ascontiguousarray(src, dtype=F32)).to(engine.device)
+    d = t.empty((dg["n"][2], dg["n"][1], dg["n"][0]), dtype=t.float32, device=engine.device)
+    B.nmd_resample_linear(engine.ctx, s, sg, dg, fill, d)
+    engine.sync()
+    return d.cpu().numpy()
+
+
+def check_resample(out, ref, src, fill):
+    outside = ref == fill
+    assert np.array_equal(out == fill, outside) or np.all(out[outside] == fill)
+    inside = ~outside
+    tol = 2.0 ** -21 * float(np.abs(src).max()) + 2.0 ** -22 * np.abs(ref[inside])
+    assert np.all(np.abs(out[inside] - ref[inside]) <= tol)
+
+
+CASES = [
+    # (src n, src spacing, src origin, dst n, dst spacing, dst origin)
+    ((37, 29, 23), (1.1, 0.9, 2.3), (-3.0, 2.0, 1.0), (31, 27, 19), (1.3, 1.0, 2.8), (-2.5, 1.5, 0.0)),
+    ((40, 33, 21), (1.0, 1.0, 2.5), (0.0, 0.0, 0.0), (13, 11, 9), (3.07, 3.01, 5.9), (0.3, -0.4, -2.0)),
+    ((9, 11, 7), (4.0, 3.0, 5.0), (0.0, 0.0, 0.0), (50, 41, 37), (0.77, 0.81, 0.95), (-1.0, -2.0, -3.0)),
+    ((64, 1, 5), (0.5, 2.0, 1.0), (1.0, 1.0, 1.0), (70, 3, 6), (0.49, 1.0, 0.9), (0.5, 0.0, 0.5)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_resample_matches_oracle(engine, case):
+    ns, ss, os_, nd, sd, od = CASES[case]
+    rng = np.random.default_rng(100 + case)
+    sg, dg = grid(ns, ss, os_), grid(nd, sd, od)
+    src = rng.normal(0.0, 300.0, size=(ns[2], ns[1], ns[0])).astype(F32)
+    fill = -1000.0
+    ref = I.resample_linear(src, sg, dg, fill)
+    out = gpu_resample(engine, src, sg, dg, fill)
+    check_resample(out, ref, src, fill)
+    if case >= 2:  # these destination grids reach outside the source volume
+        assert (ref == fill).any() and (out == fill).any()
+
+
+def test_resample_same_grid_is_exact(engine):
+    rng = np.random.default_rng(7)
+    g = grid((33, 17, 9), (0.5, 2.0, 1.0), (0.0, 0.0, 0.0))
+    src = rng.normal(size=(9, 17, 33)).astype(F32)
+    out = gpu_resample(engine, src, g, g, fill=0.0)
+    assert np.array_equal(out, src)
+
+
+def test_resample_full_size_sampled(engine):
+    """The benchmark's shape: a 512x512x438 CT of 1.333x1.333x2.5 mm onto the
+    256x256x320 patient grid of 2x2x3 mm (the CT field of view is larger),
+    checked on three z slabs recomputed by the oracle."""
+    rng = np.random.default_rng(11)
+    sg = grid((512, 512, 438), (4.0 / 3.0, 4.0 / 3.0, 2.5), (-85.3, -85.3, -67.5))
+    dg = grid((256, 256, 320), (2.0, 2.0, 3.0), (0.0, 0.0, 0.0))
+    src = (rng.normal(0.0, 200.0, size=(438, 512, 512))).astype(F32)
+    out = gpu_resample(engine, src, sg, dg, fill=-1000.0)
+    for z0 in (0, 157, 316):
+        sub = grid((256, 256, 4), (2.0, 2.0, 3.0), (0.0, 0.0, 3.0 * z0))
+        ref = I.resample_linear(src, sg, sub, -1000.0)
+        check_resample(out[z0:z0 + 4], ref, src, -1000.0)
+
+
+TABLE = P.SYNTHETIC_CT_TABLE
+
+
+def gpu_ct(engine, hu, table=TABLE):
+    t = engine.torch
+    h = t.from_numpy(np.ascontiguousarray(hu, dtype=F32)).to(engine.device)
+    d = t.empty(h.shape, dtype=t.float32, device=engine.device)
+    m = t.empty(h.shape, dtype=t.uint8, device=engine.device)
+    B.nmd_ct_to_phantom(engine.ctx, h, table, d, m)
+    engine.sync()
+    return d.cpu().numpy(), m.cpu().numpy()
+
+
+def test_ct_conversion_is_bit_exact(engine):
+    rng = np.random.default_rng(12)
+    hu = rng.uniform(-1300.0, 3500.0, size=300_001).astype(F32)
+    special = np.array(TABLE["hu"] + TABLE["threshold"] + [np.nan, np.inf, -np.inf, -1e30, 1e30],
+                       dtype=F32)
+    hu[:len(special)] = special
+    hu[len(special):len(special) + 1000] = np.nextafter(
+        np.repeat(special[:8], 125), np.float32(np.inf)).astype(F32)
+    d, m = gpu_ct(engine, hu)
+    rd, rm = I.ct_to_phantom(hu, TABLE)
+    assert np.array_equal(m, rm)
+    assert np.array_equal(d, rd)
+
+
+def test_ct_conversion_rejects_bad_tables(engine):
+    t = engine.torch
+    h = t.zeros(16, dtype=t.float32, device=engine.device)
+    d = t.empty(16, dtype=t.float32, device=engine.device)
+    m = t.empty(16, dtype=t.uint8, device=engine.device)
+    bad = [dict(TABLE, hu=[0.0, 0.0, 1.0], density=[1.0, 1.0, 1.0]),      # HU not increasing
+           dict(TABLE, density=[0.0012, 0.26, 0.0, 1.85, 2.9]),            # density <= 0
+           dict(TABLE, levels=[64, 64, 64, 65]),                           # 257 levels
+           dict(TABLE, density_min=[-1.0, 0.05, 0.7975, 1.0875])]          # centre <= 0
+    for tb in bad:
+        with pytest.raises(RuntimeError, match="NMD_E_INVALID"):
+            B.nmd_ct_to_phantom(engine.ctx, h, tb, d, m)
+
+
+def test_fused_ingestion_equals_the_two_calls(engine):
+    """nmd_ct_ingest against nmd_resample_linear (fill -1000) followed by
+    nmd_ct_to_phantom, bit for bit, on a CT that reaches past the dose grid."""
+    prob = P.patient_phantom(shape=(80, 64, 64), voxel_mm=(8.0, 8.0, 12.0), seed=9)
+    hu, ctg, phg = P.render_ct(prob, factor=(1.5, 1.5, 1.2), pad_mm=(-20.0, 30.0, 12.0))
+    t = engine.torch
+    v = gpu_resample(engine, hu, ctg, phg, fill=-1000.0)
+    d2, m2 = gpu_ct(engine, v)
+    src = t.from_numpy(hu).to(engine.device)
+    nx, ny, nz = phg["n"]
+    d = t.empty((nz, ny, nx), dtype=t.float32, device=engine.device)
+    m = t.empty((nz, ny, nx), dtype=t.uint8, device=engine.device)
+    B.nmd_ct_ingest(engine.ctx, src, ctg, phg, TABLE, d, m)
+    engine.sync()
+    assert np.array_equal(d.cpu().numpy(), d2) and np.array_equal(m.cpu().numpy(), m2)
+    assert (v == -1000.0).any()  # the CT (cropped in x) leaves part of the grid outside
+
+
+def test_ct_ingestion_end_to_end():
+    """A synthetic CT rendered from a phantom on a finer, larger grid goes
+    through both kernels and becomes a phantom the engine transports; its
+    materials agree with the phantom's away from material boundaries."""
+    prob = P.patient_phantom(shape=(80, 64, 64), voxel_mm=(8.0, 8.0, 12.0), seed=9)
+    hu, ctg, phg = P.render_ct(prob)
+    eng = B.Engine(0)  # its own context: a fresh set of material-density pairs
+    try:
+        v = gpu_resample(eng, hu, ctg, phg, fill=-1000.0)
+        ref = I.resample_linear(hu, ctg, phg, -1000.0)
+        check_resample(v, ref, hu, -1000.0)
+        d, m = gpu_ct(eng, v)
+        rd, rm = I.ct_to_phantom(v, TABLE)
+        assert np.array_equal(m, rm) and np.array_equal(d, rd)
+        assert (m == prob.material).mean() > 0.98
+        names = list(P.CT_MATERIAL_NAMES)
+        ct_prob = P.Problem(name="ct", density=d, material=m, label=prob.label,
+                            activity=prob.activity, voxel_mm=prob.voxel_mm,
+                            materials=[P.MATERIALS[k][:2] for k in names],
+                            n_organs=prob.n_organs, organ_names=prob.organ_names,
+                            total_activity_bq=prob.total_activity_bq)
+        eng.set_problem(0, ct_prob)
+        eng.run(0, 2 * 10 ** 6, 5)
+        rate, rel = eng.dose(0)
+        r_o, _, _ = eng.organs(0)
+        led = eng.ledger(0)
+        assert np.isfinite(rate.cpu().numpy()).all()
+        assert (r_o > 0).sum() >= 20
+        assert led["emitted"] > 0
+    finally:
+        eng.close()
