@@ -365,7 +365,7 @@ HBM_PEAK = 8.0e12  # bytes/s
 # HBM bytes of one ingest_kernel launch on the benchmark's CT: FETCH_SIZE x 2
 # + WRITE_SIZE of rocprofv3 --pmc runs scaled against a profiled 256 MiB copy
 # (profiles/ingest_ct512x512x438_to_patient256x256x320.md)
-INGEST_TRAFFIC_BYTES = (149434.6 * 2 + 102426.7) * 1024
+INGEST_TRAFFIC_BYTES = (147495.2 * 2 + 102400.0) * 1024
 
 
 def cpu_baseline_ingest(hu, ct_grid, ph_grid, target_s):

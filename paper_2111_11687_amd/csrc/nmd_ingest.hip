@@ -1,8 +1,7 @@
 // CT ingestion (Section 2.1 and 2.2): trilinear resampling onto the dose
-// grid and HU to density and material.  Both kernels stream their output
+// grid and HU to density and material.  The kernels stream their output
 // once (one thread per output voxel, x fastest, so writes coalesce and the
-// source gathers of neighbouring threads share cache lines): they are bound
-// by HBM bandwidth.
+// source gathers of neighbouring threads share cache lines).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -49,14 +48,13 @@ __device__ __forceinline__ Cell axis_cell(const Axis &a, int32_t i) {
   return c;
 }
 
-// Value of destination voxel v (x fastest) of a resampling.
-__device__ __forceinline__ float resample_at(const ResampleArgs &a, uint64_t v) {
+// Value of destination voxel (x, y, z) of a resampling.
+__device__ __forceinline__ float resample_at(const ResampleArgs &a, int32_t x, int32_t y,
+                                             int32_t z) {
   // no fused multiply-add, so that the fused ingestion reproduces the
   // resampled values bit for bit
 #pragma clang fp contract(off)
-  const uint64_t nx = a.nd[0], ny = a.nd[1];
   const uint64_t sx = a.ax[0].n_s, sxy = sx * (uint64_t)a.ax[1].n_s;
-  const int32_t x = (int32_t)(v % nx), y = (int32_t)((v / nx) % ny), z = (int32_t)(v / (nx * ny));
   const Cell cx = axis_cell(a.ax[0], x), cy = axis_cell(a.ax[1], y), cz = axis_cell(a.ax[2], z);
   if (!(cx.inside && cy.inside && cz.inside)) return a.fill;
   const float *p0 = a.src + cz.i0 * sxy, *p1 = a.src + cz.i1 * sxy;
@@ -91,10 +89,12 @@ __device__ __forceinline__ void ct_convert(float h, const nmd_ct_table &t, float
   material = (uint8_t)m;
 }
 
+// Launch grid (ceil(nx / 256), ny, nz): one thread per destination voxel,
+// its coordinates straight from the block and thread indices.
 __global__ __launch_bounds__(256) void resample_kernel(ResampleArgs a) {
-  const uint64_t n = (uint64_t)a.nd[0] * a.nd[1] * a.nd[2];
-  for (uint64_t v = blockIdx.x * 256ull + threadIdx.x; v < n; v += (uint64_t)gridDim.x * 256)
-    a.dst[v] = resample_at(a, v);
+  const int32_t x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.nd[0]) return;
+  a.dst[((uint64_t)z * a.nd[1] + y) * a.nd[0] + x] = resample_at(a, x, y, z);
 }
 
 __global__ __launch_bounds__(256) void ct_kernel(const float *hu, int64_t n, nmd_ct_table t,
@@ -108,16 +108,21 @@ __global__ __launch_bounds__(256) void ct_kernel(const float *hu, int64_t n, nmd
   }
 }
 
+// Launch grid as resample_kernel.
 __global__ __launch_bounds__(256) void ingest_kernel(ResampleArgs a, nmd_ct_table t,
                                                      float *density, uint8_t *material) {
-  const uint64_t n = (uint64_t)a.nd[0] * a.nd[1] * a.nd[2];
-  for (uint64_t v = blockIdx.x * 256ull + threadIdx.x; v < n; v += (uint64_t)gridDim.x * 256) {
-    float d;
-    uint8_t m;
-    ct_convert(resample_at(a, v), t, d, m);
-    density[v] = d;
-    material[v] = m;
-  }
+  const int32_t x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= a.nd[0]) return;
+  const uint64_t v = ((uint64_t)z * a.nd[1] + y) * a.nd[0] + x;
+  float d;
+  uint8_t m;
+  ct_convert(resample_at(a, x, y, z), t, d, m);
+  density[v] = d;
+  material[v] = m;
+}
+
+dim3 voxel_grid(const nmd_grid *g) {
+  return dim3((unsigned)((g->n[0] + 255) / 256), (unsigned)g->n[1], (unsigned)g->n[2]);
 }
 
 unsigned grid_blocks(uint64_t work) {
@@ -198,7 +203,7 @@ nmd_status nmd_resample_linear(nmd_ctx *c, const float *src, const nmd_grid *sg,
   const uint64_t nd = (uint64_t)dg->n[0] * dg->n[1] * dg->n[2];
   if (overlap(src, ns * 4, dst, nd * 4))
     return ctx_fail(c, NMD_E_INVALID, "source and destination overlap");
-  hipLaunchKernelGGL(resample_kernel, dim3(grid_blocks(nd)), dim3(256), 0, ctx_stream(c),
+  hipLaunchKernelGGL(resample_kernel, voxel_grid(dg), dim3(256), 0, ctx_stream(c),
                      resample_args(src, sg, dg, fill, dst));
   return ctx_hip(c, hipGetLastError(), "resample_kernel");
 }
@@ -216,7 +221,7 @@ nmd_status nmd_ct_ingest(nmd_ctx *c, const float *ct, const nmd_grid *cg, const 
   if (overlap(ct, ns * 4, density, nd * 4) || overlap(ct, ns * 4, material, nd) ||
       overlap(density, nd * 4, material, nd))
     return ctx_fail(c, NMD_E_INVALID, "CT, density and material overlap");
-  hipLaunchKernelGGL(ingest_kernel, dim3(grid_blocks(nd)), dim3(256), 0, ctx_stream(c),
+  hipLaunchKernelGGL(ingest_kernel, voxel_grid(dg), dim3(256), 0, ctx_stream(c),
                      resample_args(ct, cg, dg, -1000.0f, nullptr), *t, density, material);
   return ctx_hip(c, hipGetLastError(), "ingest_kernel");
 }
