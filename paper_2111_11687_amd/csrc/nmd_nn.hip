@@ -126,7 +126,9 @@ __device__ __forceinline__ void stage_halo(uint16_t *s, const Src &src, int cbas
 }
 
 template <int CC, int NCB>
-__global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
+// 16 input channels into one column block: four waves per SIMD (the plain K
+// loop fits 128 registers), which beats the pipelined loop at three
+__global__ __launch_bounds__(256, (NCB == 1 && CC == 16) ? 4 : 1) void conv_kernel(ConvArgs a) {
   constexpr int NC8 = CC / 8;
   constexpr int P = halo_pitch(CC);
   constexpr int NP = 27 * NC8;          // (tap, 8-channel group) pairs per chunk
@@ -177,6 +179,18 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
       for (int rb = 0; rb < 4; ++rb)
         av[rb] = *reinterpret_cast<const u32x4_t *>(s_x + rowoff[rb] + aoff);
     };
+    if constexpr (NCB == 1 && CC == 16) {
+#pragma unroll 2
+      for (int s = 0; s < NS; ++s) {
+        u32x4_t av[4], b[NCB];
+        load_step(s, av, b);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mfma_bf16(av[rb], b[cb], acc[rb][cb]);
+      }
+      continue;
+    }
     // software pipeline: step s + 1's fragments load during step s's MFMAs
     u32x4_t av[4], b[NCB], avn[4], bn[NCB];
     load_step(0, av, b);
