@@ -52,7 +52,7 @@ enum {
   NMD_E_OOM = -4,         /* device allocation failed                     */
   NMD_E_HIP = -5,         /* HIP runtime error; the context is unusable   */
   NMD_E_ABORTED = -6,     /* run stopped by the abort hook                */
-  NMD_E_UNSUPPORTED = -7  /* input outside what this build handles        */
+  NMD_E_UNSUPPORTED = -7  /* input outside what the library handles       */
 };
 
 /* One material: effective atomic number and electron fraction Z/A.  The
