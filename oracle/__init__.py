@@ -62,7 +62,9 @@ class _Opts(ctypes.Structure):
                 ("tracking", ctypes.c_int32), ("kn_method", ctypes.c_int32),
                 ("wide_uniforms", ctypes.c_int32), ("source_kind", ctypes.c_int32),
                 ("pencil_origin", ctypes.c_double * 3), ("pencil_dir", ctypes.c_double * 3),
-                ("n_threads", ctypes.c_int32), ("hist_out", ctypes.c_void_p)]
+                ("n_threads", ctypes.c_int32), ("hist_out", ctypes.c_void_p),
+                ("electron_cutoff_mev", ctypes.c_double),
+                ("mean_excitation_ev", ctypes.c_void_p)]
 
 
 class _Tally(ctypes.Structure):
@@ -104,6 +106,16 @@ def lib():
         L.orc_majorant.argtypes = [ctypes.POINTER(_Phantom), d]
         L.orc_rotate.restype = None
         L.orc_rotate.argtypes = [vp, d, d]
+        for name in ("orc_stopping_power",):
+            getattr(L, name).restype = d
+            getattr(L, name).argtypes = [d, d, d]
+        L.orc_csda_range.restype = d
+        L.orc_csda_range.argtypes = [d, d, d, d]
+        L.orc_energy_after.restype = d
+        L.orc_energy_after.argtypes = [d, d, d, d, d]
+        L.orc_electron_walk.restype = ctypes.c_int
+        L.orc_electron_walk.argtypes = [ctypes.POINTER(_Phantom), vp, d, vp, vp, d, vp, vp,
+                                        ctypes.c_int, ctypes.POINTER(d)]
         _lib = L
     return _lib
 
@@ -162,6 +174,37 @@ def rotate(d, cost: float, uphi: float) -> np.ndarray:
     v = np.array(d, dtype=np.float64)
     lib().orc_rotate(_ptr(v), float(cost), float(uphi))
     return v
+
+
+def stopping_power(t_mev: float, z_over_a: float, i_ev: float) -> float:
+    """Electron collision stopping power, MeV cm^2/g (Bethe, no density effect)."""
+    return lib().orc_stopping_power(t_mev, z_over_a, i_ev)
+
+
+def csda_range(t_lo: float, t_hi: float, z_over_a: float, i_ev: float) -> float:
+    """Mass path (g/cm^2) from t_hi down to t_lo."""
+    return lib().orc_csda_range(t_lo, t_hi, z_over_a, i_ev)
+
+
+def energy_after(t: float, mass_path: float, t_floor: float, z_over_a: float,
+                 i_ev: float) -> float:
+    return lib().orc_energy_after(t, mass_path, t_floor, z_over_a, i_ev)
+
+
+def electron_walk(ph, mean_excitation_ev, cutoff_mev: float, r, d, t0: float, cap: int = 4096):
+    """One straight-ahead CSDA electron walk; returns (deposits, escaped) with
+    deposits a list of (flat voxel, MeV) in crossing order."""
+    iev = np.ascontiguousarray(mean_excitation_ev, dtype=np.float64)
+    rr = np.ascontiguousarray(r, dtype=np.float64)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    vo = np.zeros(cap, dtype=np.int64)
+    eo = np.zeros(cap, dtype=np.float64)
+    esc = ctypes.c_double(0.0)
+    n = lib().orc_electron_walk(ctypes.byref(ph._c), _ptr(iev), cutoff_mev, _ptr(rr), _ptr(dd),
+                                t0, _ptr(vo), _ptr(eo), cap, ctypes.byref(esc))
+    if n > cap:
+        raise ValueError("more deposits than cap")
+    return [(int(vo[k]), float(eo[k])) for k in range(n)], esc.value
 
 
 # --------------------------------------------------------------------------
@@ -227,13 +270,16 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
         first_hist: int = 0, pid: int = 0, photons_per_decay: int = 2,
         process_mask: int = 7, max_real_events: int = 0, cutoff_mev: float = 0.010,
         tracking: int = TRACK_EXACT, kn_method: int | None = None, wide: bool | None = None,
-        pencil=None, n_threads: int = 0, history_records: bool = False):
+        pencil=None, n_threads: int = 0, history_records: bool = False,
+        electron_cutoff_mev: float = 0.0, mean_excitation_ev=None):
     """Run n_hist histories; returns (tally, per-history records or None).
 
     ``pencil=(origin_cm, direction)`` selects a pencil-beam source.  The
     defaults follow the tracking mode: exact traversal uses Kahn's sampler and
     53-bit uniforms; Woodcock replays the device draw order (Butcher-Messel,
-    23-bit uniforms).
+    23-bit uniforms).  ``electron_cutoff_mev > 0`` walks Compton electrons
+    above it straight ahead (CSDA; needs ``mean_excitation_ev`` per
+    material); 0 deposits them on the spot.
     """
     if tally is None:
         tally = Tally(ph)
@@ -258,6 +304,15 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
             raise ValueError("phantom has no activity map")
     o.n_threads = n_threads
     o.hist_out = _ptr(rec)
+    iev = None
+    if electron_cutoff_mev > 0.0:
+        if mean_excitation_ev is None:
+            raise ValueError("electron transport needs mean_excitation_ev per material")
+        iev = np.ascontiguousarray(mean_excitation_ev, dtype=np.float64)
+        if iev.shape != (len(ph.z_eff),):
+            raise ValueError("one mean excitation energy per material")
+    o.electron_cutoff_mev = float(electron_cutoff_mev)
+    o.mean_excitation_ev = _ptr(iev)
     rc = lib().orc_run(ctypes.byref(ph._c), ctypes.byref(o), ctypes.byref(tally._c))
     if rc != 0:
         raise ValueError("oracle rejected the input (code %d)" % rc)

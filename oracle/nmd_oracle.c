@@ -346,6 +346,9 @@ typedef struct {
   double pencil_dir[3];
   int32_t n_threads;              /* 0 = OpenMP default */
   double *hist_out;               /* [n_hist][ORC_HREC_N] or NULL */
+  double electron_cutoff_mev;     /* 0: electrons deposit on the spot; > 0: Compton
+                                     electrons above it walk straight ahead (CSDA) */
+  const double *mean_excitation_ev; /* [n_mat], eV; needed when the cutoff is > 0 */
 } orc_opts;
 
 /* Accumulators.  S, S2: [nvox]; O, O2: [n_organs + 1]; all caller-owned
@@ -467,9 +470,166 @@ static int choose_event(double t, double muc, double mupe, double mur)
   return ORC_EV_NULL;
 }
 
+/* ------------------------------------------------------------------ */
+/* Electrons above the electron cutoff (Section 2.1 tracks them down   */
+/* to 200 keV): continuous slowing down along a straight line          */
+/* ------------------------------------------------------------------ */
+#define ORC_HALF_K 0.1535375 /* 2 pi r_e^2 m_e c^2 N_A, MeV cm^2 / mol */
+
+/* Bethe collision stopping power for electrons in MeV cm^2/g (the ICRU
+ * Report 37 form with the Moller term F-), no density-effect term. */
+double orc_stopping_power(double t, double z_over_a, double i_ev)
+{
+  const double tau = t / ORC_MEC2_MEV;
+  const double g = tau + 1.0;
+  const double b2 = 1.0 - 1.0 / (g * g);
+  const double fm = 1.0 - b2 + (tau * tau / 8.0 - (2.0 * tau + 1.0) * log(2.0)) / (g * g);
+  const double ir = i_ev * 1e-6 / ORC_MEC2_MEV;
+  return ORC_HALF_K * z_over_a / b2 * (log(tau * tau * (tau + 2.0) / (2.0 * ir * ir)) + fm);
+}
+
+/* Mass path (g/cm^2) over which an electron slows from t_hi to t_lo: the
+ * integral of dT / S(T), by 8-point Gauss-Legendre on 16 equal panels. */
+double orc_csda_range(double t_lo, double t_hi, double z_over_a, double i_ev)
+{
+  static const double x[4] = { 0.1834346424956498, 0.5255324099163290, 0.7966664774136267,
+                               0.9602898564975363 };
+  static const double w[4] = { 0.3626837833783620, 0.3137066458778873, 0.2223810344533745,
+                               0.1012285362903763 };
+  if (!(t_hi > t_lo)) return 0.0;
+  const int panels = 16;
+  const double h = (t_hi - t_lo) / panels;
+  double acc = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    const double c = t_lo + (p + 0.5) * h;
+    for (int q = 0; q < 4; ++q)
+      acc += w[q] * (1.0 / orc_stopping_power(c - 0.5 * h * x[q], z_over_a, i_ev) +
+                     1.0 / orc_stopping_power(c + 0.5 * h * x[q], z_over_a, i_ev));
+  }
+  return 0.5 * h * acc;
+}
+
+/* Kinetic energy after a mass path p from t, for p short of the range down
+ * to t_floor: the root T1 of csda_range(T1, t) = p by Newton's method
+ * (d/dT1 csda_range(T1, t) = -1 / S(T1)), kept inside [t_floor, t]. */
+double orc_energy_after(double t, double p, double t_floor, double z_over_a, double i_ev)
+{
+  if (p <= 0.0) return t;
+  double t1 = t - p * orc_stopping_power(t, z_over_a, i_ev);
+  if (t1 < t_floor) t1 = t_floor;
+  for (int it = 0; it < 60; ++it) {
+    const double f = orc_csda_range(t1, t, z_over_a, i_ev) - p;
+    double nt = t1 + f * orc_stopping_power(t1, z_over_a, i_ev);
+    if (nt < t_floor) nt = t_floor;
+    if (nt > t) nt = t;
+    const double dt = fabs(nt - t1);
+    t1 = nt;
+    if (dt <= 1e-15 * t) break;
+  }
+  return t1;
+}
+
+/* Walk one electron of kinetic energy t0 > cutoff from r (inside voxel
+ * (iv0, iv1, iv2)) along the unit direction de, voxel by voxel.  In each
+ * voxel it loses what its mass path rho * s takes off the range; in the
+ * voxel where the range above the cutoff runs out it leaves all it still
+ * has.  Calls dep(v, e) per voxel; returns the energy carried out of the
+ * grid. */
+typedef void (*orc_dep_fn)(void *user, int64_t v, double e);
+
+static double electron_walk(const orc_phantom *ph, const double *i_ev, double cutoff,
+                            const double r[3], const int64_t iv_in[3], const double de[3],
+                            double t0, orc_dep_fn dep, void *user)
+{
+  const int32_t n[3] = { ph->nx, ph->ny, ph->nz };
+  const double h[3] = { ph->dx, ph->dy, ph->dz };
+  int64_t iv[3] = { iv_in[0], iv_in[1], iv_in[2] };
+  double tnext[3], tstep[3];
+  int stp[3];
+  for (int a = 0; a < 3; ++a) {
+    if (de[a] > 0.0) {
+      stp[a] = 1;
+      tnext[a] = ((double)(iv[a] + 1) * h[a] - r[a]) / de[a];
+      tstep[a] = h[a] / de[a];
+    } else if (de[a] < 0.0) {
+      stp[a] = -1;
+      tnext[a] = ((double)iv[a] * h[a] - r[a]) / de[a];
+      tstep[a] = -h[a] / de[a];
+    } else {
+      stp[a] = 0;
+      tnext[a] = INFINITY;
+      tstep[a] = INFINITY;
+    }
+    if (tnext[a] < 0.0) tnext[a] = 0.0;
+  }
+  double t = t0, s_cur = 0.0;
+  for (;;) {
+    const int64_t v = iv[0] + (int64_t)n[0] * (iv[1] + (int64_t)n[1] * iv[2]);
+    const int m = ph->material[v];
+    const double rho = ph->density[v];
+    const double za = ph->z_over_a[m], ie = i_ev[m];
+    int ax = 0;
+    if (tnext[1] < tnext[ax]) ax = 1;
+    if (tnext[2] < tnext[ax]) ax = 2;
+    const double seg = tnext[ax] - s_cur;
+    if (rho * seg >= orc_csda_range(cutoff, t, za, ie)) {
+      dep(user, v, t);
+      return 0.0;
+    }
+    const double t1 = orc_energy_after(t, rho * seg, cutoff, za, ie);
+    dep(user, v, t - t1);
+    t = t1;
+    s_cur = tnext[ax];
+    iv[ax] += stp[ax];
+    tnext[ax] += tstep[ax];
+    if (iv[ax] < 0 || iv[ax] >= n[ax]) return t;
+  }
+}
+
 /* Handle a real event at voxel v.  Returns 1 when the photon ends. */
-static int do_event(const orc_ctx *cx, orc_stream *st, int ev, int64_t v, double *E, double d[3],
-                    dep_list *l, orc_local *loc, int *n_real)
+typedef struct {
+  dep_list *l;
+  orc_local *loc;
+} walk_sink;
+
+static void walk_deposit(void *user, int64_t v, double e)
+{
+  walk_sink *w = (walk_sink *)user;
+  add_dep(w->l, w->loc, v, e, L_DEP_C);
+}
+
+/* The Compton electron of energy te at position r in voxel v: deposited on
+ * the spot, or, above the electron cutoff, walked along its recoil
+ * momentum E d_in - E' d_out. */
+static void compton_electron(const orc_ctx *cx, int64_t v, const double r[3], const double d_in[3],
+                             const double d_out[3], double e, double e1, dep_list *l,
+                             orc_local *loc)
+{
+  const orc_phantom *ph = cx->ph;
+  const double te = e - e1;
+  double p[3], pn = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    p[a] = e * d_in[a] - e1 * d_out[a];
+    pn += p[a] * p[a];
+  }
+  pn = sqrt(pn);
+  if (!(pn > 0.0)) {
+    add_dep(l, loc, v, te, L_DEP_C);
+    return;
+  }
+  for (int a = 0; a < 3; ++a) p[a] /= pn;
+  const int64_t iv[3] = { v % ph->nx, (v / ph->nx) % ph->ny, v / ((int64_t)ph->nx * ph->ny) };
+  walk_sink sink = { l, loc };
+  const double esc = electron_walk(ph, cx->op->mean_excitation_ev, cx->op->electron_cutoff_mev,
+                                   r, iv, p, te, walk_deposit, &sink);
+  if (esc > 0.0) {
+    loc->ledger[L_ESC] += esc;
+    loc->rec[1] += esc;
+  }
+}
+
+static int do_event(const orc_ctx *cx, orc_stream *st, int ev, int64_t v, const double r[3],
+                    double *E, double d[3], dep_list *l, orc_local *loc, int *n_real)
 {
   const orc_opts *op = cx->op;
   (*n_real)++;
@@ -482,8 +642,14 @@ static int do_event(const orc_ctx *cx, orc_stream *st, int ev, int64_t v, double
                                                     : sample_kn_butcher(st, k, &cost);
     const double uphi = stream_uniform(st);
     const double e1 = eps * *E;
-    add_dep(l, loc, v, *E - e1, L_DEP_C);
-    rotate_dir(d, cost, uphi);
+    if (op->electron_cutoff_mev > 0.0 && *E - e1 > op->electron_cutoff_mev) {
+      const double d_in[3] = { d[0], d[1], d[2] };
+      rotate_dir(d, cost, uphi);
+      compton_electron(cx, v, r, d_in, d, *E, e1, l, loc);
+    } else {
+      add_dep(l, loc, v, *E - e1, L_DEP_C);
+      rotate_dir(d, cost, uphi);
+    }
     *E = e1;
     if (*E < op->cutoff_mev) {
       add_dep(l, loc, v, *E, L_DEP_CUT);
@@ -552,7 +718,7 @@ static void photon_woodcock(const orc_ctx *cx, orc_stream *st, double r[3], doub
       loc->stats[S_NULL]++;
       continue;
     }
-    if (do_event(cx, st, ev, v, &E, d, l, loc, &n_real)) return;
+    if (do_event(cx, st, ev, v, r, &E, d, l, loc, &n_real)) return;
   }
 }
 
@@ -637,7 +803,7 @@ static void photon_exact(const orc_ctx *cx, orc_stream *st, double r[3], int64_t
       loc->stats[S_NULL]++;
       continue;
     }
-    if (do_event(cx, st, ev, v, &E, d, l, loc, &n_real)) return;
+    if (do_event(cx, st, ev, v, r, &E, d, l, loc, &n_real)) return;
   }
 }
 
@@ -772,6 +938,11 @@ int orc_run(const orc_phantom *ph, const orc_opts *op, orc_tally *tal)
       ph->n_mat > 8)
     return -1;
   if (op->photons_per_decay < 1 || op->photons_per_decay > 2) return -1;
+  if (op->electron_cutoff_mev > 0.0) {
+    if (!op->mean_excitation_ev) return -1;
+    for (int m = 0; m < ph->n_mat; ++m)
+      if (!(op->mean_excitation_ev[m] > 0.0)) return -1;
+  }
   const int64_t nvox = (int64_t)ph->nx * ph->ny * ph->nz;
   for (int64_t v = 0; v < nvox; ++v) {
     if (ph->material[v] >= ph->n_mat || !(ph->density[v] > 0.0) || isinf(ph->density[v]))
@@ -984,3 +1155,44 @@ double orc_majorant(const orc_phantom *ph, double e)
 }
 
 void orc_rotate(double *d, double cost, double uphi) { rotate_dir(d, cost, uphi); }
+
+/* One electron walk for the tests: r (cm) inside the grid, de a unit
+ * direction.  Writes up to cap deposits (voxel, MeV) and the escaped
+ * energy; returns the number of deposits (which may exceed cap). */
+typedef struct {
+  int64_t *v;
+  double *e;
+  int n, cap;
+} walk_out;
+
+static void walk_collect(void *user, int64_t v, double e)
+{
+  walk_out *o = (walk_out *)user;
+  if (o->n < o->cap) {
+    o->v[o->n] = v;
+    o->e[o->n] = e;
+  }
+  o->n++;
+}
+
+int orc_electron_walk(const orc_phantom *ph, const double *i_ev, double cutoff, const double *r,
+                      const double *de, double t0, int64_t *v_out, double *e_out, int cap,
+                      double *escaped)
+{
+  const int32_t n[3] = { ph->nx, ph->ny, ph->nz };
+  const double h[3] = { ph->dx, ph->dy, ph->dz };
+  int64_t iv[3];
+  for (int a = 0; a < 3; ++a) {
+    int64_t i = (int64_t)floor(r[a] / h[a]);
+    iv[a] = i < 0 ? 0 : (i >= n[a] ? n[a] - 1 : i);
+  }
+  walk_out o = { v_out, e_out, 0, cap };
+  *escaped = 0.0;
+  if (t0 <= cutoff) {
+    walk_collect(&o, iv[0] + (int64_t)n[0] * (iv[1] + (int64_t)n[1] * iv[2]), t0);
+    return o.n;
+  }
+  *escaped = electron_walk(ph, i_ev, cutoff, r, iv, de, t0, walk_collect, &o);
+  return o.n;
+}
+

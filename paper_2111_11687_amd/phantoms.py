@@ -31,6 +31,12 @@ MATERIALS = {
     "bone":        (12.3, 0.515, 1.85),
 }
 
+# Mean excitation energies (eV) for electron stopping powers, ICRU Report 37
+# values for liquid water, dry air, ICRP lung, ICRP soft tissue and ICRU
+# compact bone.
+MEAN_EXCITATION_EV = {"water": 75.0, "air": 85.7, "lung": 75.3, "soft_tissue": 72.3,
+                      "bone": 91.9}
+
 # The 27 organs of Table 1, in the table's order (labels 1..27); label 28 is
 # the rest of the body, label 0 is outside the body.
 ORGANS = (

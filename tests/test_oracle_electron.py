@@ -195,3 +195,87 @@ def test_walk_escape_carries_the_remaining_energy():
     t_out = El.energy_after(t0, 0.0012 * 0.25, WATER_ZA, WATER_I)
     assert esc == pytest.approx(t_out, rel=1e-10)
     assert sum(e for _, e in dep) + esc == pytest.approx(t0, rel=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# The C oracle's electron option (oracle/nmd_oracle.c), checked against the
+# pinned model above and against run-level invariants.
+# ---------------------------------------------------------------------------
+from conftest import ledger_balance, oracle_phantom  # noqa: E402
+from paper_2111_11687_amd import phantoms as P  # noqa: E402
+
+
+def test_c_primitives_match_the_pinned_model(orc):
+    for za, ie in [(WATER_ZA, WATER_I), (0.499, 85.7), (0.515, 91.9)]:
+        for t in (0.2, 0.25, 0.3407, 0.5):
+            assert orc.stopping_power(t, za, ie) == pytest.approx(
+                El.stopping_power(t, za, ie), rel=1e-14)
+            assert orc.csda_range(0.2, t, za, ie) == pytest.approx(
+                El.csda_range(0.2, t, za, ie), rel=1e-12, abs=1e-300)
+        for frac in (1e-4, 0.3, 0.95):
+            p = frac * El.csda_range(0.2, 0.3407, za, ie)
+            assert orc.energy_after(0.3407, p, 0.2, za, ie) == pytest.approx(
+                El.energy_after(0.3407, p, za, ie), rel=1e-12)
+
+
+def test_c_walk_matches_the_pinned_walk(orc):
+    rng = np.random.default_rng(21)
+    za, ie = [WATER_ZA, 0.499, 0.515], [WATER_I, 85.7, 91.9]
+    dens = rng.uniform(0.001, 1.9, size=(5, 6, 7))
+    mat = rng.integers(0, 3, size=(5, 6, 7)).astype(np.uint8)
+    h = (0.012, 0.009, 0.015)
+    ph = orc.Phantom(dens, mat, [7.4, 7.6, 12.3], za, h)
+    for _ in range(25):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        r = rng.uniform(0.0, 1.0, size=3) * np.array([7, 6, 5]) * np.array(h)
+        t0 = rng.uniform(0.2, 0.3407)
+        a, ea = orc.electron_walk(ph, ie, 0.2, r, d, t0)
+        b, eb = El.csda_walk(dens, mat, h, za, ie, r, d, t0)
+        assert [v for v, _ in a] == [v for v, _ in b]
+        assert np.allclose([e for _, e in a], [e for _, e in b], rtol=1e-10, atol=1e-15)
+        assert ea == pytest.approx(eb, rel=1e-10, abs=1e-15)
+
+
+def _patient(n=(40, 32, 32), seed=9):
+    prob = P.patient_phantom(shape=n, voxel_mm=(8.0, 8.0, 12.0), seed=seed)
+    iev = [P.MEAN_EXCITATION_EV[next(k for k in P.MATERIALS
+                                     if tuple(P.MATERIALS[k][:2]) == tuple(m))]
+           for m in prob.materials]
+    return prob, iev
+
+
+@pytest.mark.parametrize("tracking", ["exact", "woodcock"])
+def test_electrons_keep_every_photon_draw_and_the_energy(orc, tracking):
+    """The walk draws no random numbers: with the same seed every history has
+    the same photon events and draws, and the energy it leaves plus the
+    energy it sends out is the same."""
+    prob, iev = _patient()
+    ph = oracle_phantom(orc, prob)
+    tr = orc.TRACK_EXACT if tracking == "exact" else orc.TRACK_WOODCOCK
+    t0, r0 = orc.run(ph, 4000, 5, tracking=tr, history_records=True)
+    t1, r1 = orc.run(ph, 4000, 5, tracking=tr, history_records=True,
+                     electron_cutoff_mev=0.2, mean_excitation_ev=iev)
+    assert np.array_equal(r0[:, [2, 3, 4, 5, 8]], r1[:, [2, 3, 4, 5, 8]])
+    assert np.allclose(r0[:, 0] + r0[:, 1], r1[:, 0] + r1[:, 1], rtol=1e-12, atol=1e-12)
+    assert abs(ledger_balance(t1.ledger)) < 1e-12
+    # some electrons do walk: deposits spread over more voxels
+    assert (r1[:, 7] >= r0[:, 7]).all() and (r1[:, 7] > r0[:, 7]).any()
+
+
+def test_electron_cutoff_above_the_largest_transfer_changes_nothing(orc):
+    prob, iev = _patient(n=(24, 20, 20))
+    ph = oracle_phantom(orc, prob)
+    # one thread: the tally's summation order is then fixed
+    a, _ = orc.run(ph, 3000, 8, n_threads=1)
+    b, _ = orc.run(ph, 3000, 8, n_threads=1, electron_cutoff_mev=0.35, mean_excitation_ev=iev)
+    assert np.array_equal(a.S, b.S) and np.array_equal(a.S2, b.S2)
+
+
+def test_electron_option_rejects_missing_energies(orc):
+    prob, iev = _patient(n=(24, 20, 20))
+    ph = oracle_phantom(orc, prob)
+    with pytest.raises(ValueError):
+        orc.run(ph, 10, 1, electron_cutoff_mev=0.2)
+    with pytest.raises(ValueError):
+        orc.run(ph, 10, 1, electron_cutoff_mev=0.2, mean_excitation_ev=[0.0] * len(iev))
