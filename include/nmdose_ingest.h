@@ -76,8 +76,9 @@ typedef struct {
  *     centre density_min[m] + (k + 1/2) density_width[m].
  * The levels keep the distinct (material, density) pairs of the phantom
  * within the engine's 256 (sum of levels <= 256).  Outputs: density float[n],
- * material uint8[n].  NMD_E_INVALID for a bad table (including a level
- * centre <= 0) or pointers. */
+ * material uint8[n].  density may be hu itself (converted in place); any
+ * other overlap of the three arrays is NMD_E_INVALID, as are a bad table
+ * (including a level centre <= 0) and missing pointers. */
 nmd_status nmd_ct_to_phantom(nmd_ctx *ctx, const float *hu, int64_t n, const nmd_ct_table *table,
                              float *density, uint8_t *material);
 

@@ -233,6 +233,12 @@ nmd_status nmd_ct_to_phantom(nmd_ctx *c, const float *hu, int64_t n, const nmd_c
   if (!hu || !density || !material || n < 1)
     return ctx_fail(c, NMD_E_INVALID, "hu, density, material and n >= 1 are required");
   if ((s = check_table(c, t))) return s;
+  // each element is read and written by one thread, so density may be hu
+  // itself; any other overlap would race
+  const uint64_t nb = (uint64_t)n * 4;
+  if ((hu != density && overlap(hu, nb, density, nb)) || overlap(hu, nb, material, (uint64_t)n) ||
+      overlap(density, nb, material, (uint64_t)n))
+    return ctx_fail(c, NMD_E_INVALID, "hu, density and material overlap");
   hipLaunchKernelGGL(ct_kernel, dim3(grid_blocks((uint64_t)n)), dim3(256), 0, ctx_stream(c), hu,
                      n, *t, density, material);
   return ctx_hip(c, hipGetLastError(), "ct_kernel");

@@ -128,6 +128,24 @@ def test_ct_conversion_rejects_bad_tables(engine):
             B.nmd_ct_to_phantom(engine.ctx, h, tb, d, m)
 
 
+def test_ct_conversion_in_place_and_overlap(engine):
+    """density may be the hu array itself; other overlaps are rejected."""
+    t = engine.torch
+    rng = np.random.default_rng(13)
+    hu = rng.uniform(-1100.0, 2500.0, size=4099).astype(F32)
+    rd, rm = I.ct_to_phantom(hu, TABLE)
+    buf = t.from_numpy(hu).to(engine.device)
+    m = t.empty(hu.shape, dtype=t.uint8, device=engine.device)
+    B.nmd_ct_to_phantom(engine.ctx, buf, TABLE, buf, m)
+    engine.sync()
+    assert np.array_equal(buf.cpu().numpy(), rd) and np.array_equal(m.cpu().numpy(), rm)
+    h2 = t.from_numpy(hu).to(engine.device)
+    with pytest.raises(RuntimeError, match="NMD_E_INVALID"):
+        B.nmd_ct_to_phantom(engine.ctx, h2[1:], TABLE, h2[:-1], m[:-1])
+    with pytest.raises(RuntimeError, match="NMD_E_INVALID"):
+        B.nmd_ct_to_phantom(engine.ctx, h2, TABLE, h2, h2.view(t.uint8)[:hu.size])
+
+
 def test_fused_ingestion_equals_the_two_calls(engine):
     """nmd_ct_ingest against nmd_resample_linear (fill -1000) followed by
     nmd_ct_to_phantom, bit for bit, on a CT that reaches past the dose grid."""
