@@ -351,7 +351,9 @@ def bench_denoiser(args):
                    "inference_full_phantom_ms": inf_ms},
         "roofline": {"bound": "mfma", "achieved": dom_flops / (dom_ms * 1e-3) / 1e12,
                      "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": dom_flops / (dom_ms * 1e-3) / MFMA_BF16_PEAK, "traffic": None,
+                     "frac": dom_flops / (dom_ms * 1e-3) / MFMA_BF16_PEAK,
+                     "traffic": DENOISER_DOM_TRAFFIC_BYTES,
+                     "traffic_unit": "bytes per launch (profiled)",
                      "kernel": "conv_kernel<16,1> (dec0a forward, 48->16 channels)",
                      "kernel_ms": dom_ms},
     }
@@ -360,6 +362,12 @@ def bench_denoiser(args):
     eng.close()
     print(json.dumps(res), flush=True)
 
+
+# HBM bytes of one launch of the dominant convolution (dec0a forward on the
+# 160x128x128 box): FETCH_SIZE x 2 + WRITE_SIZE of rocprofv3 --pmc runs
+# scaled against a profiled 256 MiB copy
+# (profiles/denoiser_conv_box160x128x128_counters.md)
+DENOISER_DOM_TRAFFIC_BYTES = (57974.7 * 2 + 81920.0) * 1024
 
 HBM_PEAK = 8.0e12  # bytes/s
 # HBM bytes of one ingest_kernel launch on the benchmark's CT: FETCH_SIZE x 2
