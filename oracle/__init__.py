@@ -23,6 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 TRACK_EXACT, TRACK_WOODCOCK = 0, 1
 KN_KAHN, KN_BUTCHER = 0, 1
+RNG_PHILOX, RNG_XOSHIRO = 0, 1
 SRC_ACTIVITY, SRC_PENCIL = 0, 1
 
 LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded")
@@ -64,7 +65,7 @@ class _Opts(ctypes.Structure):
                 ("pencil_origin", ctypes.c_double * 3), ("pencil_dir", ctypes.c_double * 3),
                 ("n_threads", ctypes.c_int32), ("hist_out", ctypes.c_void_p),
                 ("electron_cutoff_mev", ctypes.c_double),
-                ("mean_excitation_ev", ctypes.c_void_p)]
+                ("mean_excitation_ev", ctypes.c_void_p), ("rng", ctypes.c_int32)]
 
 
 class _Tally(ctypes.Structure):
@@ -99,7 +100,14 @@ def lib():
         L.orc_organ_stats.restype = None
         L.orc_organ_stats.argtypes = [vp, vp, vp, ctypes.c_int64, i32, vp, vp]
         L.orc_sample.restype = ctypes.c_int
-        L.orc_sample.argtypes = [ctypes.c_int, d, u64, u64, ctypes.c_int, vp]
+        L.orc_sample.argtypes = [ctypes.c_int, d, u64, u64, ctypes.c_int, ctypes.c_int, vp]
+        L.orc_sample_source.restype = ctypes.c_int
+        L.orc_sample_source.argtypes = [ctypes.POINTER(_Phantom), u64, u64, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, vp]
+        L.orc_splitmix64.restype = u64
+        L.orc_splitmix64.argtypes = [ctypes.POINTER(u64)]
+        L.orc_xoshiro256ss.restype = u64
+        L.orc_xoshiro256ss.argtypes = [ctypes.POINTER(u64 * 4)]
         L.orc_thomson_inverse.restype = d
         L.orc_thomson_inverse.argtypes = [d]
         L.orc_majorant.restype = d
@@ -155,15 +163,48 @@ _SAMPLE_WIDTH = {0: 4, 1: 1, 2: 3, 3: 2, 4: 2, 5: 1}
 
 
 def sample(kind: str, n: int, seed: int = 1, e_mev: float = 0.511,
-           wide: bool = False) -> np.ndarray:
+           wide: bool = False, rng: int = RNG_PHILOX) -> np.ndarray:
     """Draw n samples; kind in {'raw','uniform','marsaglia','kahn','butcher','thomson'}."""
     k = {"raw": 0, "uniform": 1, "marsaglia": 2, "kahn": 3, "butcher": 4, "thomson": 5}[kind]
     out = np.zeros(n * _SAMPLE_WIDTH[k], dtype=np.float64)
-    rc = lib().orc_sample(k, float(e_mev), int(n), int(seed), int(wide), _ptr(out))
+    rc = lib().orc_sample(k, float(e_mev), int(n), int(seed), int(wide), int(rng), _ptr(out))
     if rc != 0:
         raise ValueError(kind)
     w = _SAMPLE_WIDTH[k]
     return out.reshape(n, w) if w > 1 else out
+
+
+def sample_source(ph, n: int, seed: int = 1, tracking: int = TRACK_EXACT,
+                  wide: bool | None = None, rng: int | None = None):
+    """Decay points drawn as the transport draws them (Section 2.1: voxel
+    probability proportional to the activity, position uniform in the
+    voxel).  Returns (voxel index int64 [n], position cm [n, 3])."""
+    if ph.activity is None:
+        raise ValueError("phantom has no activity map")
+    if wide is None:
+        wide = tracking == TRACK_EXACT
+    if rng is None:
+        rng = RNG_XOSHIRO if tracking == TRACK_EXACT else RNG_PHILOX
+    out = np.zeros((n, 4), dtype=np.float64)
+    rc = lib().orc_sample_source(ctypes.byref(ph._c), int(n), int(seed), int(tracking),
+                                 int(bool(wide)), int(rng), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the activity map (code %d)" % rc)
+    return out[:, 0].astype(np.int64), out[:, 1:].copy()
+
+
+def splitmix64(x: int):
+    """One SplitMix64 step: (output, new state)."""
+    st = ctypes.c_uint64(x)
+    out = lib().orc_splitmix64(ctypes.byref(st))
+    return int(out), int(st.value)
+
+
+def xoshiro256ss(state, n: int):
+    """n outputs of xoshiro256** from the 4-word state (the state is not
+    modified)."""
+    st = (ctypes.c_uint64 * 4)(*[int(v) for v in state])
+    return [int(lib().orc_xoshiro256ss(ctypes.byref(st))) for _ in range(n)]
 
 
 def thomson_inverse(u: float) -> float:
@@ -271,13 +312,14 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
         process_mask: int = 7, max_real_events: int = 0, cutoff_mev: float = 0.010,
         tracking: int = TRACK_EXACT, kn_method: int | None = None, wide: bool | None = None,
         pencil=None, n_threads: int = 0, history_records: bool = False,
-        electron_cutoff_mev: float = 0.0, mean_excitation_ev=None):
+        electron_cutoff_mev: float = 0.0, mean_excitation_ev=None, rng: int | None = None):
     """Run n_hist histories; returns (tally, per-history records or None).
 
     ``pencil=(origin_cm, direction)`` selects a pencil-beam source.  The
-    defaults follow the tracking mode: exact traversal uses Kahn's sampler and
-    53-bit uniforms; Woodcock replays the device draw order (Butcher-Messel,
-    23-bit uniforms).  ``electron_cutoff_mev > 0`` walks Compton electrons
+    defaults follow the tracking mode: exact traversal uses Kahn's sampler,
+    53-bit uniforms and xoshiro256** streams (a generator family the device
+    does not use); Woodcock replays the device draw order (Philox4x32-10,
+    Butcher-Messel, 23-bit uniforms).  ``electron_cutoff_mev > 0`` walks Compton electrons
     above it straight ahead (CSDA; needs ``mean_excitation_ev`` per
     material); 0 deposits them on the spot.
     """
@@ -287,12 +329,15 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
         kn_method = KN_KAHN if tracking == TRACK_EXACT else KN_BUTCHER
     if wide is None:
         wide = tracking == TRACK_EXACT
+    if rng is None:
+        rng = RNG_XOSHIRO if tracking == TRACK_EXACT else RNG_PHILOX
     rec = np.zeros((n_hist, len(HREC_FIELDS)), dtype=np.float64) if history_records else None
     o = _Opts()
     o.n_hist, o.first_hist, o.seed, o.pid = n_hist, first_hist, seed, pid
     o.photons_per_decay, o.process_mask = photons_per_decay, process_mask
     o.max_real_events, o.cutoff_mev = max_real_events, cutoff_mev
     o.tracking, o.kn_method, o.wide_uniforms = tracking, kn_method, int(bool(wide))
+    o.rng = int(rng)
     if pencil is not None:
         o.source_kind = SRC_PENCIL
         for a in range(3):

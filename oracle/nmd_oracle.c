@@ -28,8 +28,12 @@
  *                         uniforms in the documented per-history order so a
  *                         history can be replayed draw for draw.
  * Two Klein-Nishina samplers: Kahn's rejection (1954) and the
- * Butcher-Messel composition-rejection.  Random numbers come from this
- * file's own Philox4x32-10 (Salmon et al., SC'11).
+ * Butcher-Messel composition-rejection.  Two random-number families, both
+ * written here from their published definitions: Philox4x32-10 (Salmon et
+ * al., SC'11), the device's family, which the Woodcock replay consumes in
+ * the device's order; and xoshiro256** (Blackman and Vigna 2018) seeded per
+ * history through SplitMix64, a family the device does not use, which the
+ * exact-traversal mode draws from by default.
  *
  * Parity status: every primitive here is pinned by the CPU tests against
  * closed forms, numerical integration, published generator outputs or
@@ -84,7 +88,10 @@ double orc_sigma_kn(double e_mev)
 {
   const double k = e_mev / ORC_MEC2_MEV;
   const double a = 1.0 + 2.0 * k;
-  const double l = log(a);
+  /* ln(1 + 2k) through log1p: log(a) of the rounded a loses about
+   * eps / (2k) relative, which the cancellation in the bracket below
+   * (a difference of order k^2) turns into a 5e-9 error at 1 keV */
+  const double l = log1p(2.0 * k);
   const double t1 = (1.0 + k) / (k * k) * (2.0 * (1.0 + k) / a - l / k);
   const double t2 = l / (2.0 * k);
   const double t3 = (1.0 + 3.0 * k) / (a * a);
@@ -156,8 +163,39 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Per-history stream: counter = (block, hid_lo, hid_hi, phantom_id),
- * key = (seed_lo, seed_hi).  Words are consumed in order x0..x3. */
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a Weyl sequence with
+ * increment 0x9E3779B97F4A7C15 passed through a variant-13 mix. */
+uint64_t orc_splitmix64(uint64_t *x)
+{
+  uint64_t z = (*x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static uint64_t rotl64(uint64_t x, int k) { return (x << k) | (x >> (64 - k)); }
+
+/* xoshiro256** (Blackman and Vigna 2018): output rotl(5 s1, 7) * 9, then the
+ * xorshift-rotate state update. */
+uint64_t orc_xoshiro256ss(uint64_t s[4])
+{
+  const uint64_t out = rotl64(s[1] * 5u, 7) * 9u;
+  const uint64_t t = s[1] << 17;
+  s[2] ^= s[0];
+  s[3] ^= s[1];
+  s[1] ^= s[2];
+  s[0] ^= s[3];
+  s[2] ^= t;
+  s[3] = rotl64(s[3], 45);
+  return out;
+}
+
+enum { ORC_RNG_PHILOX = 0, ORC_RNG_XOSHIRO = 1 };
+
+/* Per-history stream.  Philox: counter = (block, hid_lo, hid_hi,
+ * phantom_id), key = (seed_lo, seed_hi), words consumed in order x0..x3.
+ * xoshiro256**: state from SplitMix64 over the seed, the history id and the
+ * phantom id; each 64-bit output gives two words, high half first. */
 typedef struct {
   uint32_t key[2];
   uint32_t hid_lo, hid_hi, pid;
@@ -165,10 +203,13 @@ typedef struct {
   uint32_t buf[4];
   int pos;             /* next word in buf; 4 = empty */
   int wide;            /* 0: 23-bit uniforms (one word); 1: 53-bit (two) */
+  int rng;             /* ORC_RNG_* */
+  uint64_t xs[4];      /* xoshiro256** state */
   uint64_t n_uniform;  /* uniforms handed out */
 } orc_stream;
 
-static void stream_init(orc_stream *s, uint64_t seed, uint64_t hid, uint32_t pid, int wide)
+static void stream_init(orc_stream *s, uint64_t seed, uint64_t hid, uint32_t pid, int wide,
+                        int rng)
 {
   s->key[0] = (uint32_t)seed;
   s->key[1] = (uint32_t)(seed >> 32);
@@ -178,14 +219,29 @@ static void stream_init(orc_stream *s, uint64_t seed, uint64_t hid, uint32_t pid
   s->block = 0;
   s->pos = 4;
   s->wide = wide;
+  s->rng = rng;
   s->n_uniform = 0;
+  if (rng == ORC_RNG_XOSHIRO) {
+    uint64_t x = seed;
+    x = orc_splitmix64(&x) ^ hid;
+    x = orc_splitmix64(&x) ^ (uint64_t)pid;
+    for (int i = 0; i < 4; ++i) s->xs[i] = orc_splitmix64(&x);
+  }
 }
 
 static uint32_t stream_word(orc_stream *s)
 {
   if (s->pos == 4) {
-    uint32_t ctr[4] = { s->block, s->hid_lo, s->hid_hi, s->pid };
-    orc_philox4x32_10(ctr, s->key, s->buf);
+    if (s->rng == ORC_RNG_XOSHIRO) {
+      const uint64_t a = orc_xoshiro256ss(s->xs), b = orc_xoshiro256ss(s->xs);
+      s->buf[0] = (uint32_t)(a >> 32);
+      s->buf[1] = (uint32_t)a;
+      s->buf[2] = (uint32_t)(b >> 32);
+      s->buf[3] = (uint32_t)b;
+    } else {
+      uint32_t ctr[4] = { s->block, s->hid_lo, s->hid_hi, s->pid };
+      orc_philox4x32_10(ctr, s->key, s->buf);
+    }
     s->block++;
     s->pos = 0;
   }
@@ -349,6 +405,7 @@ typedef struct {
   double electron_cutoff_mev;     /* 0: electrons deposit on the spot; > 0: Compton
                                      electrons above it walk straight ahead (CSDA) */
   const double *mean_excitation_ev; /* [n_mat], eV; needed when the cutoff is > 0 */
+  int32_t rng;                    /* ORC_RNG_PHILOX or ORC_RNG_XOSHIRO */
 } orc_opts;
 
 /* Accumulators.  S, S2: [nvox]; O, O2: [n_organs + 1]; all caller-owned
@@ -822,13 +879,38 @@ static int64_t source_voxel(const orc_ctx *cx, double u)
   return lo;
 }
 
+/* Decay point (Section 2.1: decays follow the activity; uniform within the
+ * voxel): the voxel by CDF inversion, then three position uniforms.  The
+ * Woodcock replay mode takes the same two draws the device alias sampler
+ * takes (a raw word for the index and a uniform for the accept test); it
+ * inverts the CDF with the raw word. */
+static void sample_decay(const orc_ctx *cx, orc_stream *st, int64_t iv0[3], double r0[3])
+{
+  const orc_phantom *ph = cx->ph;
+  int64_t v;
+  if (cx->op->tracking == ORC_TRACK_WOODCOCK) {
+    const uint32_t x = stream_word(st);
+    st->n_uniform++;
+    (void)stream_uniform(st);
+    v = source_voxel(cx, ((double)x + 0.5) / 4294967296.0);
+  } else {
+    v = source_voxel(cx, stream_uniform(st));
+  }
+  iv0[0] = v % ph->nx;
+  iv0[1] = (v / ph->nx) % ph->ny;
+  iv0[2] = v / ((int64_t)ph->nx * ph->ny);
+  r0[0] = ((double)iv0[0] + stream_uniform(st)) * ph->dx;
+  r0[1] = ((double)iv0[1] + stream_uniform(st)) * ph->dy;
+  r0[2] = ((double)iv0[2] + stream_uniform(st)) * ph->dz;
+}
+
 static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local *loc,
                         const orc_tally *tal)
 {
   const orc_phantom *ph = cx->ph;
   const orc_opts *op = cx->op;
   orc_stream st;
-  stream_init(&st, op->seed, hid, op->pid, op->wide_uniforms);
+  stream_init(&st, op->seed, hid, op->pid, op->wide_uniforms, op->rng);
   memset(loc->rec, 0, sizeof(loc->rec));
   l->n = 0;
 
@@ -845,24 +927,7 @@ static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local 
     iv0[1] = (int64_t)floor(r0[1] / ph->dy);
     iv0[2] = (int64_t)floor(r0[2] / ph->dz);
   } else {
-    /* Decay voxel.  The Woodcock replay mode takes the same two draws the
-     * device alias sampler takes (a raw word for the index and a uniform
-     * for the accept test); it inverts the CDF with the raw word. */
-    int64_t v;
-    if (op->tracking == ORC_TRACK_WOODCOCK) {
-      const uint32_t x = stream_word(&st);
-      st.n_uniform++;
-      (void)stream_uniform(&st);
-      v = source_voxel(cx, ((double)x + 0.5) / 4294967296.0);
-    } else {
-      v = source_voxel(cx, stream_uniform(&st));
-    }
-    iv0[0] = v % ph->nx;
-    iv0[1] = (v / ph->nx) % ph->ny;
-    iv0[2] = v / ((int64_t)ph->nx * ph->ny);
-    r0[0] = ((double)iv0[0] + stream_uniform(&st)) * ph->dx;
-    r0[1] = ((double)iv0[1] + stream_uniform(&st)) * ph->dy;
-    r0[2] = ((double)iv0[2] + stream_uniform(&st)) * ph->dz;
+    sample_decay(cx, &st, iv0, r0);
     sample_marsaglia(&st, d0);
   }
   for (int p = 0; p < nph; ++p) {
@@ -1097,12 +1162,13 @@ void orc_organ_stats(const double *dose_rate, const double *rel_unc, const uint8
 /* kind 0: raw Philox words; 1: uniforms; 2: Marsaglia directions (3 per
  * sample); 3: Kahn KN (eps, cos); 4: Butcher-Messel KN (eps, cos);
  * 5: Thomson cos.  Sample i uses the stream of history i. */
-int orc_sample(int kind, double e_mev, uint64_t n, uint64_t seed, int wide, double *out)
+int orc_sample(int kind, double e_mev, uint64_t n, uint64_t seed, int wide, int rng,
+               double *out)
 {
   const double k = e_mev / ORC_MEC2_MEV;
   for (uint64_t i = 0; i < n; ++i) {
     orc_stream st;
-    stream_init(&st, seed, i, 0, wide);
+    stream_init(&st, seed, i, 0, wide, rng);
     switch (kind) {
     case 0:
       for (int j = 0; j < 4; ++j) out[4 * i + j] = (double)stream_word(&st);
@@ -1126,6 +1192,54 @@ int orc_sample(int kind, double e_mev, uint64_t n, uint64_t seed, int wide, doub
       return -1;
     }
   }
+  return 0;
+}
+
+/* Decay points of a phantom's activity map, as the transport draws them:
+ * out[4 i] = voxel index, out[4 i + 1 .. 3] = position (cm).  Sample i uses
+ * the stream of history i; tracking selects the draw order (exact: one
+ * uniform for the voxel; Woodcock: the device's raw word and accept
+ * uniform).  Returns 0, or a negative value on invalid input. */
+int orc_sample_source(const orc_phantom *ph, uint64_t n, uint64_t seed, int tracking, int wide,
+                      int rng, double *out)
+{
+  const int64_t nvox = (int64_t)ph->nx * ph->ny * ph->nz;
+  double *cdf = (double *)malloc(sizeof(double) * (size_t)nvox);
+  double acc = 0.0;
+  for (int64_t v = 0; v < nvox; ++v) {
+    const double a = ph->activity[v];
+    if (!(a >= 0.0) || isinf(a)) {
+      free(cdf);
+      return -3;
+    }
+    acc += a;
+    cdf[v] = acc;
+  }
+  if (!(acc > 0.0)) {
+    free(cdf);
+    return -3;
+  }
+  orc_opts op;
+  memset(&op, 0, sizeof op);
+  op.tracking = tracking;
+  orc_ctx cx;
+  memset(&cx, 0, sizeof cx);
+  cx.ph = ph;
+  cx.op = &op;
+  cx.cdf = cdf;
+  cx.nvox = nvox;
+  for (uint64_t i = 0; i < n; ++i) {
+    orc_stream st;
+    stream_init(&st, seed, i, 0, wide, rng);
+    int64_t iv[3];
+    double r[3];
+    sample_decay(&cx, &st, iv, r);
+    out[4 * i] = (double)(iv[0] + (int64_t)ph->nx * (iv[1] + (int64_t)ph->ny * iv[2]));
+    out[4 * i + 1] = r[0];
+    out[4 * i + 2] = r[1];
+    out[4 * i + 3] = r[2];
+  }
+  free(cdf);
   return 0;
 }
 

@@ -62,7 +62,8 @@ def run_case(name):
 
 if __name__ == "__main__":
     out = {"generator": "tests/golden/make_oracle_reference.py",
-           "oracle": "oracle/nmd_oracle.c, exact traversal, Kahn KN sampler, 53-bit uniforms"}
+           "oracle": "oracle/nmd_oracle.c, exact traversal, Kahn KN sampler, 53-bit uniforms "
+                     "from xoshiro256** streams"}
     for name in CASES:
         out[name] = run_case(name)
     with open(os.path.join(HERE, "oracle_reference.json"), "w") as f:

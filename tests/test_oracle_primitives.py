@@ -97,14 +97,14 @@ def _kn_dsigma_dcos(e, c):
 def test_sigma_kn_against_integrated_differential(orc, e):
     val, _ = integrate.quad(lambda c: _kn_dsigma_dcos(e, c), -1.0, 1.0, epsabs=0,
                             epsrel=1e-13, limit=200)
-    assert orc.sigma_kn(e) == pytest.approx(val, rel=1e-10)
+    assert orc.sigma_kn(e) == pytest.approx(val, rel=1e-10, abs=0)
 
 
 def test_sigma_kn_thomson_limit(orc):
     sig_t = 8.0 * math.pi / 3.0 * RE * RE
     # first-order low-energy expansion: sigma = sigma_T (1 - 2k + ...)
     k = 1e-3 / MEC2
-    assert orc.sigma_kn(1e-3) == pytest.approx(sig_t * (1 - 2 * k + 5.2 * k * k), rel=1e-6)
+    assert orc.sigma_kn(1e-3) == pytest.approx(sig_t * (1 - 2 * k + 5.2 * k * k), rel=1e-6, abs=0)
 
 
 def test_cross_section_anchors_and_scaling(orc):
@@ -112,30 +112,30 @@ def test_cross_section_anchors_and_scaling(orc):
         c = orc.mass_atten(1, 7.4, zoa, 0.030, interp=False)
         pe = orc.mass_atten(2, 7.4, zoa, 0.030, interp=False)
         r = orc.mass_atten(3, 7.4, zoa, 0.030, interp=False)
-        assert pe == pytest.approx(c, rel=1e-13)       # PE equals Compton at 30 keV, Z 7.4
-        assert r == pytest.approx(0.1 * c, rel=1e-13)  # Rayleigh is a tenth of it
-        assert c == pytest.approx(NA * zoa * orc.sigma_kn(0.030), rel=1e-14)
+        assert pe == pytest.approx(c, rel=1e-13, abs=0)       # PE equals Compton at 30 keV, Z 7.4
+        assert r == pytest.approx(0.1 * c, rel=1e-13, abs=0)  # Rayleigh is a tenth of it
+        assert c == pytest.approx(NA * zoa * orc.sigma_kn(0.030), rel=1e-14, abs=0)
     # per-atom Z^4 and Z^2 laws -> per-gram Z^3 and Z at fixed Z/A
     z1, z2 = 7.4, 12.3
     assert orc.mass_atten(2, z2, 0.5, 0.1, False) / orc.mass_atten(2, z1, 0.5, 0.1, False) == \
-        pytest.approx((z2 / z1) ** 3, rel=1e-13)
+        pytest.approx((z2 / z1) ** 3, rel=1e-13, abs=0)
     assert orc.mass_atten(3, z2, 0.5, 0.1, False) / orc.mass_atten(3, z1, 0.5, 0.1, False) == \
-        pytest.approx(z2 / z1, rel=1e-13)
+        pytest.approx(z2 / z1, rel=1e-13, abs=0)
     # energy laws E^-3, E^-2
     assert orc.mass_atten(2, z1, 0.5, 0.05, False) / orc.mass_atten(2, z1, 0.5, 0.1, False) == \
-        pytest.approx(8.0, rel=1e-13)
+        pytest.approx(8.0, rel=1e-13, abs=0)
     assert orc.mass_atten(3, z1, 0.5, 0.05, False) / orc.mass_atten(3, z1, 0.5, 0.1, False) == \
-        pytest.approx(4.0, rel=1e-13)
+        pytest.approx(4.0, rel=1e-13, abs=0)
 
 
 def test_log_grid_and_interpolation(orc):
     e = np.array([orc.grid_energy(i) for i in range(256)])
-    assert e[0] == pytest.approx(1e-3, rel=1e-15) and e[-1] == pytest.approx(0.511, rel=1e-14)
+    assert e[0] == pytest.approx(1e-3, rel=1e-15, abs=0) and e[-1] == pytest.approx(0.511, rel=1e-14, abs=0)
     assert np.allclose(np.diff(np.log(e)), math.log(511.0) / 255.0, rtol=1e-12, atol=0)
     # nodes reproduced; power laws exact between nodes; KN within 1.1e-5
     for i in (0, 17, 128, 254):
         assert orc.mass_atten(1, 7.4, 0.55, e[i]) == pytest.approx(
-            orc.mass_atten(1, 7.4, 0.55, e[i], interp=False), rel=1e-13)
+            orc.mass_atten(1, 7.4, 0.55, e[i], interp=False), rel=1e-13, abs=0)
     grid = np.exp(np.linspace(math.log(0.0105), math.log(0.5105), 3001))
     err = max(abs(orc.mass_atten(1, 7.4, 0.55, x) / orc.mass_atten(1, 7.4, 0.55, x, False) - 1)
               for x in grid)
@@ -154,7 +154,7 @@ def test_water_attenuation_at_511(orc):
     ne = NA * 0.5551
     mu = ne * (sig511 + sig30 * (0.030 / 0.511) ** 3 + 0.1 * sig30 * (0.030 / 0.511) ** 2)
     got = sum(orc.mass_atten(p, 7.4, 0.5551, 0.511) for p in (1, 2, 3))
-    assert got == pytest.approx(mu, rel=2e-6)
+    assert got == pytest.approx(mu, rel=2e-6, abs=0)
     assert 0.0958 < got < 0.0960
 
 

@@ -36,10 +36,10 @@ def test_energy_conservation(orc, tracking):
     ph = _oracle_phantom(orc, prob)
     tal, _ = orc.run(ph, 20000, 3, tracking=tracking)
     assert abs(_balance(tal.ledger)) < 1e-9
-    assert tal.ledger["emitted"] == pytest.approx(2 * 20000 * 0.511, rel=1e-12)
+    assert tal.ledger["emitted"] == pytest.approx(2 * 20000 * 0.511, rel=1e-12, abs=0)
     s = float(tal.S.sum())
     dep = tal.ledger["dep_compton"] + tal.ledger["dep_pe"] + tal.ledger["dep_cutoff"]
-    assert s == pytest.approx(dep, rel=1e-12)
+    assert s == pytest.approx(dep, rel=1e-12, abs=0)
 
 
 @pytest.mark.parametrize("tracking", [0, 1])
@@ -121,15 +121,15 @@ def test_total_absorption_cell_fixes_dose_units_and_merge(orc, tracking):
                        history_records=True)
     assert tal.ledger["escaped"] == 0.0
     assert (rec[:, 2] >= 1).mean() > 0.5  # most histories deposit in several pieces
-    assert tal.S[0, 0, 0] == pytest.approx(N * 0.511, rel=1e-12)
-    assert tal.S2[0, 0, 0] == pytest.approx(N * 0.511 ** 2, rel=1e-12)
+    assert tal.S[0, 0, 0] == pytest.approx(N * 0.511, rel=1e-12, abs=0)
+    assert tal.S2[0, 0, 0] == pytest.approx(N * 0.511 ** 2, rel=1e-12, abs=0)
     rate, eps = orc.finalize(ph, tal, a_ts_bq=1.0)
     m_kg = 20.0 * 1e6 * 1e-3
-    assert rate[0, 0, 0] == pytest.approx(0.511 * J_PER_MEV / m_kg, rel=1e-12)
+    assert rate[0, 0, 0] == pytest.approx(0.511 * J_PER_MEV / m_kg, rel=1e-12, abs=0)
     assert eps[0, 0, 0] < 1e-6
     # organ mean by per-history scores equals the map mean (Eq. 2)
     org_rate, rel = orc.organ_mean_sigma(tal, 1.0)
-    assert org_rate[0] == pytest.approx(rate[0, 0, 0], rel=1e-12)
+    assert org_rate[0] == pytest.approx(rate[0, 0, 0], rel=1e-12, abs=0)
 
 
 def test_walters_variance_on_toy_tallies(orc):
@@ -146,13 +146,13 @@ def test_walters_variance_on_toy_tallies(orc):
     tal.n_decays = N
     rate, eps = orc.finalize(ph, tal, a_ts_bq=1.0)
     p = k / N
-    assert eps[0, 0, 0] == pytest.approx(math.sqrt((1 - p) / (p * (N - 1))), rel=1e-12)
+    assert eps[0, 0, 0] == pytest.approx(math.sqrt((1 - p) / (p * (N - 1))), rel=1e-12, abs=0)
     assert eps[0, 0, 1] < 1e-7
     assert eps[0, 0, 2] == 0.0 and rate[0, 0, 2] == 0.0
     # Eq. 2 and Eq. 3 on the toy map: mean of rates, RMS of relative errors
     r, e = orc.organ_stats(ph, rate, eps)
-    assert r[0] == pytest.approx(rate.mean(), rel=1e-14)
-    assert e[0] == pytest.approx(math.sqrt((eps ** 2).mean()), rel=1e-14)
+    assert r[0] == pytest.approx(rate.mean(), rel=1e-14, abs=0)
+    assert e[0] == pytest.approx(math.sqrt((eps ** 2).mean()), rel=1e-14, abs=0)
 
 
 def test_point_source_cube_symmetry(orc):

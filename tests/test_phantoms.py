@@ -38,7 +38,7 @@ def test_patient_phantom_organs_and_activity():
     assert np.all(p.activity[p.label > 0] >= 0)
     vol = np.prod(p.voxel_cm)
     assert p.activity.astype(np.float64).sum() * vol == pytest.approx(p.total_activity_bq,
-                                                                        rel=1e-5)
+                                                                        rel=1e-5, abs=0)
     assert p.total_activity_bq == pytest.approx(8.0 * 3.7e7 * 0.5 ** (60 / 109.77))
     lungs = (p.label == P.ORGANS.index("Lung_Left") + 1)
     assert np.all(p.density[lungs] == np.float32(0.26))
