@@ -57,7 +57,11 @@ def test_statistical_parity(engine, orc, name):
     elif name == "slab128":
         prob, ng, no, nv_min = P.slab_phantom(), 10 ** 7, 2 * 10 ** 6, 150
     else:  # too few voxels reach 5 % at these sizes: organs only
-        prob, ng, no, nv_min = P.patient_phantom(), 10 ** 7, 10 ** 6, 0
+        # the oracle sample sets the power here: at 10^6 decays the scores of
+        # the small organs (tens of histories hit them) are too skewed for the
+        # normal bar, and seed 2002's Spinal_Cord mean sits 3.1 sigma from the
+        # oracle's own 10^8-decay run; at 4 x 10^6 it sits within 1.8
+        prob, ng, no, nv_min = P.patient_phantom(), 10 ** 7, 4 * 10 ** 6, 0
     gd, ge, gr, gs, led, st = _gpu(engine, 20, prob, ng, 1001)
     od, oe, orr, os_, _ = _oracle(orc, prob, no, 2002)
     assert abs(ledger_balance(led)) < 1e-9
@@ -70,6 +74,39 @@ def test_statistical_parity(engine, orc, name):
         p, nv, red = _voxel_p(gd, ge, od, oe, prob.density)
         print(name, "voxel chi2/dof %.4f over %d voxels, p = %.4f" % (red, nv, p))
         assert nv >= nv_min and p > 0.01
+
+
+def test_statistical_parity_photon_cutoff(engine, orc):
+    """The slab with Section 2.1's photon cutoff raised to 150 keV, against
+    the exact-traversal oracle with the same cutoff: organs within three
+    combined sigma, the voxel chi-square, a cutoff deposit on both sides and
+    both ledgers closed."""
+    prob = P.slab_phantom()
+    engine.set_problem(23, prob)
+    engine.run(23, 10 ** 7, 3003, photon_cutoff_mev=0.15)
+    gd, ge = (t.cpu().numpy() for t in engine.dose(23))
+    gr, _, gs = engine.organs(23)
+    led = engine.ledger(23)
+    ph = oracle_phantom(orc, prob)
+    # 10^7 oracle decays: at 2 x 10^6 the voxels that pass the 5 % cut are
+    # chosen on a noisy sigma estimate, which inflates the chi-square (two
+    # oracle runs, 10^7 and 2 x 10^6 decays, already give chi2/dof 1.2 there)
+    tal, _ = orc.run(ph, 10 ** 7, 4004, cutoff_mev=0.15)
+    a = prob.total_activity_bq
+    od, oe = orc.finalize(ph, tal, a)
+    orr, os_ = orc.organ_mean_sigma(tal, a)
+    oled = tal.ledger
+    assert led["dep_cutoff"] > 0.0 and oled["dep_cutoff"] > 0.0
+    assert abs(ledger_balance(led)) < 1e-9 and abs(ledger_balance(oled)) < 1e-9
+    # the cutoff's share of the deposited energy agrees within its binomial noise
+    share = lambda l: l["dep_cutoff"] / (l["dep_compton"] + l["dep_pe"] + l["dep_cutoff"])  # noqa: E731
+    assert share(led) == pytest.approx(share(oled), rel=2e-2, abs=0)
+    z, m = _organ_z(gr, gs, orr, os_)
+    print("cutoff 150 keV organ z:", np.round(z, 2))
+    assert m.sum() >= 8 and np.all(np.abs(z) <= 3.0)
+    p, nv, red = _voxel_p(gd, ge, od, oe, prob.density)
+    print("cutoff 150 keV voxel chi2/dof %.4f over %d voxels, p = %.4f" % (red, nv, p))
+    assert nv >= 1000 and p > 0.01
 
 
 def _reference():

@@ -26,11 +26,14 @@ def _replay(engine, orc, pid, prob, n, seed, **kw):
     for k in ("photons_per_decay", "process_mask", "max_real_events"):
         if k in kw:
             okw[k] = kw[k]
+    if "photon_cutoff_mev" in kw:
+        okw["cutoff_mev"] = kw["photon_cutoff_mev"]
     engine.run(pid, n, seed, history_records=rec, **gkw)
     g = rec.cpu().numpy().reshape(n, 10)
     ph = oracle_phantom(orc, prob)
-    _, o = orc.run(ph, n, seed, tracking=orc.TRACK_WOODCOCK, pid=pid, history_records=True,
-                   **okw)
+    tal, o = orc.run(ph, n, seed, tracking=orc.TRACK_WOODCOCK, pid=pid, history_records=True,
+                     **okw)
+    _replay.oracle_ledger = tal.ledger
     return g, o
 
 
@@ -77,6 +80,23 @@ def test_replay_masks_and_first_collision(engine, orc):
     g, o = _replay(engine, orc, 13, prob, 20_000, 12, process_mask=2 | 4)
     _check(g, o)
     assert g[:, 2].sum() == 0
+
+
+def test_replay_photon_cutoff(engine, orc):
+    """Section 2.1's photon cutoff raised to 150 keV, so that it ends a large
+    share of the scattered photons: the branch that leaves E' in the voxel of
+    the event replays history by history, both ledgers book a cutoff deposit
+    and each closes to 1e-9."""
+    prob = P.slab_phantom(n=64, voxel_mm=6.0)
+    g, o = _replay(engine, orc, 15, prob, 30_000, 17, photon_cutoff_mev=0.15)
+    _check(g, o)
+    led, oled = engine.ledger(15), _replay.oracle_ledger
+    assert led["dep_cutoff"] > 0.0 and oled["dep_cutoff"] > 0.0
+    # the same histories end by the cutoff on both sides: totals agree to
+    # FP32 rounding of the energies (the few replay misses aside)
+    assert led["dep_cutoff"] == pytest.approx(oled["dep_cutoff"], rel=1e-2, abs=0)
+    assert abs(ledger_balance(led)) < 1e-9
+    assert abs(ledger_balance(oled)) < 1e-9
 
 
 def test_replay_full_size_patient_pencil(engine, orc):
