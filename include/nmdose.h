@@ -85,7 +85,12 @@ typedef struct {
 
 /* Ledger slots (MeV) and run-stats slots.  NMD_STAT_LIST_MERGES counts the
  * histories that deposited in more organs than the per-history organ slots
- * hold (three), whose organ scores were merged from the deposit list. */
+ * hold (three), whose organ scores were merged from the deposit list.
+ * NMD_STAT_OVERFLOWS counts deposits of histories whose list of distinct
+ * deposit voxels (64) was full: each is scored on its own, so every mean
+ * (Eq. 1, Eq. 2) stays exact but the history's square for that voxel and
+ * organ is split, which biases the uncertainties low; a nonzero count marks
+ * them as approximate. */
 enum { NMD_LEDGER_EMITTED = 0, NMD_LEDGER_DEP_COMPTON, NMD_LEDGER_DEP_PE, NMD_LEDGER_DEP_CUTOFF,
        NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_N };
 enum { NMD_STAT_HISTORIES = 0, NMD_STAT_PHOTONS, NMD_STAT_STEPS, NMD_STAT_NULLS,
@@ -142,8 +147,11 @@ nmd_status nmd_set_activity(nmd_ctx *ctx, int32_t phantom_id, const float *activ
  * of phantom p draws its random numbers from Philox4x32-10 with key = seed
  * and counter = (block, h, p), so repeated calls continue one stream and the
  * result does not depend on the launch shape.  opts NULL = defaults.
- * Asynchronous; returns NMD_E_ABORTED (after synchronising) when the abort
- * hook fired. */
+ * Asynchronous, except with the abort hook armed (abort_after_chunks > 0):
+ * then the run scores into scratch tallies, synchronises, and adds them to
+ * the phantom's only if the hook did not fire; NMD_E_ABORTED leaves the
+ * tallies, organ sums, ledger, counters and history count as before the
+ * call. */
 nmd_status nmd_run_histories(nmd_ctx *ctx, int32_t phantom_id, uint64_t n_decays, uint64_t seed,
                              const nmd_run_opts *opts);
 
@@ -222,9 +230,30 @@ nmd_status nmd_get_tallies(nmd_ctx *ctx, int32_t phantom_id, double *sum_dev, do
 /* Replace the sums S_v, S2_v (device or host double[nvox] each) and the
  * decay count N of a phantom, e.g. to resume from values read with
  * nmd_get_tallies.  The per-history organ scores, ledger and counters are
- * zeroed.  Synchronises the stream. */
+ * zeroed, so they no longer cover all N histories: until the next reset,
+ * nmd_get_organ_score, and nmd_get_organ_dose / nmd_read_organ_dose with a
+ * rel_sigma_mean output, return NMD_E_STATE (Eq. 1-3 from the voxel sums
+ * stay available).  nmd_save / nmd_load carry the whole state instead.
+ * Synchronises the stream. */
 nmd_status nmd_set_tallies(nmd_ctx *ctx, int32_t phantom_id, const double *sum,
                            const double *sum2, uint64_t n_decays);
+
+/* Checkpoint of a phantom's Monte Carlo state: the voxel sums S_v, S2_v of
+ * the history-by-history method (Section 2.1), the per-history organ sums
+ * behind the organ-mean uncertainty, the energy ledger, the run counters and
+ * the history count N, which is also the next history id, so a run after
+ * nmd_load into the same phantom id (the id is part of every history's
+ * random stream) with the same seed continues the same streams, and runs
+ * split by a save/load equal one run of their total.  nmd_save writes the
+ * host file `path` (through a temporary file renamed on success).
+ * nmd_load requires the phantom to be registered with the same geometry
+ * (dimensions, voxel size, records) and activity map as when saved
+ * (NMD_E_STATE otherwise; NMD_E_INVALID for an unreadable, truncated or
+ * corrupted file, detected by a 64-bit checksum), and leaves the phantom
+ * unchanged on any error.  A(t_s) of Eq. 1 is the one currently set.
+ * Both synchronise the stream. */
+nmd_status nmd_save(nmd_ctx *ctx, int32_t phantom_id, const char *path);
+nmd_status nmd_load(nmd_ctx *ctx, int32_t phantom_id, const char *path);
 
 /* ---- test hooks ----------------------------------------------------------- */
 

@@ -70,6 +70,9 @@ struct Phantom {
   bool has_label = false;
   double a_ts = 0.0;
   uint64_t n_done = 0;
+  uint64_t organ_from = 0;  // histories run before the organ sums O, O2 started
+  uint64_t geom_hash = 0;   // FNV-1a of the voxel records, for checkpoints
+  uint64_t act_hash = 0;    // FNV-1a of the alias table, for checkpoints
   double vkg() const { return dx * dy * dz * 1.0e-3; }  // kg per (g/cm^3)
 };
 
@@ -189,7 +192,7 @@ Phantom *find(nmd_ctx *c, int32_t id) {
   return it == c->ph.end() ? nullptr : &it->second;
 }
 
-nmd_status upload_desc(nmd_ctx *c, int32_t id, Phantom &p) {
+PhantomDesc make_desc(int32_t id, const Phantom &p) {
   PhantomDesc d = {};
   d.rec = p.rec.as<uint16_t>();
   d.alias = p.alias.as<uint4>();
@@ -215,9 +218,24 @@ nmd_status upload_desc(nmd_ctx *c, int32_t id, Phantom &p) {
   d.inv_dz = (float)(1.0 / p.dz);
   d.n_alias = p.n_alias;
   d.pid = (uint32_t)id;
+  return d;
+}
+
+nmd_status upload_desc(nmd_ctx *c, int32_t id, Phantom &p) {
+  const PhantomDesc d = make_desc(id, p);
   HIP_TRY(c, hipMemcpyAsync(c->d_desc.as<PhantomDesc>() + id, &d, sizeof d, hipMemcpyHostToDevice,
                             c->stream));
   return sync(c);
+}
+
+// 64-bit FNV-1a over a byte range, continuing from h.
+uint64_t fnv1a(const void *data, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+  const unsigned char *b = static_cast<const unsigned char *>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
 }
 
 nmd_status zero_tallies(nmd_ctx *c, Phantom &p) {
@@ -227,6 +245,7 @@ nmd_status zero_tallies(nmd_ctx *c, Phantom &p) {
   HIP_TRY(c, launch_zero_bytes(p.stats.p, p.stats.n, c->stream));
   HIP_TRY(c, launch_set_u64(p.n_done_dev.as<unsigned long long>(), 0ull, c->stream));
   p.n_done = 0;
+  p.organ_from = 0;
   return NMD_OK;
 }
 
@@ -408,17 +427,80 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
 // Enqueue one run: clear the queue, transport, advance the history
 // counters.  Host mirrors of the counters advance at enqueue time.
 nmd_status enqueue_run(nmd_ctx *c, RunPlan &pl, unsigned long long *queue, uint32_t *dep_v,
-                       double *dep_e, uint32_t *dep_r, hipStream_t st) {
+                       double *dep_e, uint32_t *dep_r, hipStream_t st, bool advance = true) {
   pl.rp.queue = queue;
   pl.rp.dep_v = dep_v;
   pl.rp.dep_e = dep_e;
   pl.rp.dep_r = dep_r;
   HIP_TRY(c, launch_zero_bytes(queue, 2 * sizeof(unsigned long long), st));
   HIP_TRY(c, launch_transport(pl.rp, pl.grid, pl.debug, st));
+  if (!advance) return NMD_OK;
   uint64_t n = pl.rp.n_ph ? pl.rp.slot[0].n_hist : 0;
   HIP_TRY(c, launch_advance(pl.rp.desc, pl.ids, n, st));
   for (int i = 0; i < pl.ids.n; ++i) c->ph[pl.ids.id[i]].n_done += n;
   return NMD_OK;
+}
+
+// Scoring buffers of one phantom for a run that may be stopped by the abort
+// hook: the run scores into these, and they are added to the phantom's own
+// only once it has finished, so a stopped run leaves no trace.
+struct RunScratch {
+  DevBuf tally, organ, ledger, stats;
+};
+
+// A run with the abort hook armed: transport into zeroed scratch scoring
+// buffers (through a copy of the descriptor table that points at them),
+// then, if the hook did not fire, add them to the phantoms' tallies and
+// advance the history counters.  On NMD_E_ABORTED the phantoms are as
+// before the call.
+nmd_status run_abortable(nmd_ctx *c, RunPlan &pl) {
+  nmd_status s;
+  std::vector<RunScratch> scr(pl.ids.n);
+  DevBuf desc;
+  if ((s = dev_alloc(c, desc, c->d_desc.n))) return s;
+  HIP_TRY(c, hipMemcpyAsync(desc.p, c->d_desc.p, c->d_desc.n, hipMemcpyDeviceToDevice,
+                            c->stream));
+  for (int i = 0; i < pl.ids.n; ++i) {
+    const int32_t id = pl.ids.id[i];
+    Phantom &p = c->ph[id];
+    RunScratch &r = scr[i];
+    if ((s = dev_alloc(c, r.tally, p.tally.n)) || (s = dev_alloc(c, r.organ, p.organ.n)) ||
+        (s = dev_alloc(c, r.ledger, p.ledger.n)) || (s = dev_alloc(c, r.stats, p.stats.n)))
+      return s;
+    for (DevBuf *b : {&r.tally, &r.organ, &r.ledger, &r.stats})
+      HIP_TRY(c, launch_zero_bytes(b->p, b->n, c->stream));
+    PhantomDesc d = make_desc(id, p);
+    d.tally = r.tally.as<double2>();
+    d.organ = r.organ.as<double2>();
+    d.ledger = r.ledger.as<double>();
+    d.stats = r.stats.as<unsigned long long>();
+    HIP_TRY(c, hipMemcpyAsync(desc.as<PhantomDesc>() + id, &d, sizeof d, hipMemcpyHostToDevice,
+                              c->stream));
+  }
+  pl.rp.desc = desc.as<PhantomDesc>();
+  if ((s = enqueue_run(c, pl, c->d_queue.as<unsigned long long>(), c->d_dep_v.as<uint32_t>(),
+                       c->d_dep_e.as<double>(), c->d_dep_r.as<uint32_t>(), c->stream, false)))
+    return s;
+  pl.rp.desc = c->d_desc.as<PhantomDesc>();
+  unsigned long long q[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(q, c->d_queue.p, sizeof q, hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c))) return s;
+  if (q[1]) return fail(c, NMD_E_ABORTED, "run stopped by the abort hook; tallies unchanged");
+  for (int i = 0; i < pl.ids.n; ++i) {
+    Phantom &p = c->ph[pl.ids.id[i]];
+    RunScratch &r = scr[i];
+    HIP_TRY(c, launch_add_f64(p.tally.as<double>(), r.tally.as<double>(), p.nvox * 2, c->stream));
+    HIP_TRY(c, launch_add_f64(p.organ.as<double>(), r.organ.as<double>(),
+                              (uint64_t)(p.n_org + 1) * 2, c->stream));
+    HIP_TRY(c, launch_add_f64(p.ledger.as<double>(), r.ledger.as<double>(), NMD_LEDGER_N,
+                              c->stream));
+    HIP_TRY(c, launch_add_stats(p.stats.as<unsigned long long>(),
+                                r.stats.as<unsigned long long>(), c->stream));
+  }
+  const uint64_t n = pl.rp.n_ph ? pl.rp.slot[0].n_hist : 0;
+  HIP_TRY(c, launch_advance(pl.rp.desc, pl.ids, n, c->stream));
+  for (int i = 0; i < pl.ids.n; ++i) c->ph[pl.ids.id[i]].n_done += n;
+  return sync(c);
 }
 
 nmd_status enqueue_organ_reduce(nmd_ctx *c, Phantom &p, hipStream_t st) {
@@ -629,6 +711,14 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
   p.nvox = nvox;
   p.organ_count = count;
   p.used = used;
+  {
+    const int32_t hd[3] = {nx, ny, nz};
+    uint64_t h = fnv1a(hd, sizeof hd);
+    h = fnv1a(rec.data(), rec.size() * sizeof(uint16_t), h);
+    for (int q = 0; q < kMaxPalette; ++q)
+      if (used[q]) h = fnv1a(&pal[q].c, sizeof(float4), h);
+    p.geom_hash = h;
+  }
 
   // majorant nodes: max over this phantom's pairs of the total attenuation
   std::vector<float> maj(kNGrid);
@@ -734,6 +824,7 @@ nmd_status nmd_set_activity(nmd_ctx *c, int32_t id, const float *act, double tot
   HIP_TRY(c, hipMemcpyAsync(d.p, tab.data(), n * sizeof(uint4), hipMemcpyHostToDevice, c->stream));
   if ((s = sync(c))) return s;
   p->alias = std::move(d);
+  p->act_hash = fnv1a(tab.data(), tab.size() * sizeof(uint4));
   p->gen = c->next_gen++;
   p->n_alias = (uint32_t)n;
   p->has_activity = true;
@@ -762,6 +853,12 @@ nmd_status nmd_run_histories(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
   RunPlan plan;
   if ((s = plan_run(c, id, n, seed, opts_in, plan))) return s;
   if (n == 0) return NMD_OK;
+  if (plan.abort_after) {
+    s = run_abortable(c, plan);
+    c->last_chunk = plan.rp.chunk;
+    c->last_grid = (uint32_t)plan.grid;
+    return s;
+  }
   const bool tune = plan.auto_chunk && !plan.tuned && n >= kTuneMinPerPhantom;
   if (!tune) {
     if ((s = enqueue_run(c, plan, c->d_queue.as<unsigned long long>(), c->d_dep_v.as<uint32_t>(),
@@ -805,12 +902,6 @@ nmd_status nmd_run_histories(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed,
   }
   c->last_chunk = plan.rp.chunk;
   c->last_grid = (uint32_t)plan.grid;
-  if (plan.abort_after) {
-    unsigned long long q[2] = {0, 0};
-    HIP_TRY(c, hipMemcpyAsync(q, c->d_queue.p, sizeof q, hipMemcpyDeviceToHost, c->stream));
-    if ((s = sync(c))) return s;
-    if (q[1]) return fail(c, NMD_E_ABORTED, "run stopped by the abort hook");
-  }
   return NMD_OK;
 }
 
@@ -839,6 +930,12 @@ nmd_status nmd_read_organ_dose(nmd_ctx *c, int32_t id, int32_t n_organs, double 
     return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
   if (n_organs < 0 || n_organs > p->n_org)
     return fail(c, NMD_E_INVALID, "n_organs %d exceeds the phantom's %d", n_organs, p->n_org);
+  if (sig_mean && p->organ_from != 0)
+    return fail(c, NMD_E_STATE,
+                "phantom %d: the per-history organ sums cover %llu of %llu histories (sums "
+                "restored by nmd_set_tallies); restore with nmd_load for the organ sigma",
+                id, (unsigned long long)(p->n_done - p->organ_from),
+                (unsigned long long)p->n_done);
   const double n = (double)p->n_done;
   std::vector<double> acc((p->n_org + 1) * 2);
   std::vector<double2> org(p->n_org + 1);
@@ -907,6 +1004,10 @@ nmd_status nmd_get_organ_score(nmd_ctx *c, int32_t id, int32_t n_organs, double 
   if (n_organs < 0 || n_organs > p->n_org || !rate)
     return fail(c, NMD_E_INVALID, "bad n_organs or output");
   if (p->n_done == 0) return fail(c, NMD_E_STATE, "phantom %d has no histories yet", id);
+  if (p->organ_from != 0)
+    return fail(c, NMD_E_STATE,
+                "phantom %d: the per-history organ sums do not cover the histories restored "
+                "by nmd_set_tallies", id);
   std::vector<double2> org(p->n_org + 1);
   HIP_TRY(c, hipMemcpyAsync(org.data(), p->organ.p, org.size() * sizeof(double2),
                             hipMemcpyDeviceToHost, c->stream));
@@ -976,7 +1077,127 @@ nmd_status nmd_set_tallies(nmd_ctx *c, int32_t id, const double *sum, const doub
                               c->stream));
   HIP_TRY(c, launch_set_u64(p->n_done_dev.as<unsigned long long>(), n, c->stream));
   p->n_done = n;
+  p->organ_from = n;
   return sync(c);
+}
+
+// ---- checkpoints ------------------------------------------------------------
+// File layout (little-endian): a header, then the (S, S2) pairs of every
+// voxel, the (O, O2) pairs of labels 0..n_org, the ledger and the run
+// counters, then a 64-bit FNV-1a of everything before it.
+namespace {
+struct CkptHeader {
+  char magic[8];            // "NMDCKPT1"
+  uint32_t version, n_org;  // 1
+  int32_t nx, ny, nz, pad;
+  uint64_t nvox, n_done, organ_from;
+  uint64_t geom_hash, act_hash;
+  double dx, dy, dz;
+};
+constexpr size_t kLedgerSlots = 8, kStatSlots = 16;
+}  // namespace
+
+nmd_status nmd_save(nmd_ctx *c, int32_t id, const char *path) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->has_activity) return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
+  if (!path) return fail(c, NMD_E_INVALID, "path is required");
+  CkptHeader h = {};
+  std::memcpy(h.magic, "NMDCKPT1", 8);
+  h.version = 1;
+  h.n_org = (uint32_t)p->n_org;
+  h.nx = p->nx;
+  h.ny = p->ny;
+  h.nz = p->nz;
+  h.nvox = p->nvox;
+  h.n_done = p->n_done;
+  h.organ_from = p->organ_from;
+  h.geom_hash = p->geom_hash;
+  h.act_hash = p->act_hash;
+  h.dx = p->dx;
+  h.dy = p->dy;
+  h.dz = p->dz;
+  std::vector<double> tal, org, led;
+  std::vector<unsigned long long> st;
+  if ((s = to_host(c, tal, p->tally.as<double>(), p->nvox * 2)) ||
+      (s = to_host(c, org, p->organ.as<double>(), (uint64_t)(p->n_org + 1) * 2)) ||
+      (s = to_host(c, led, p->ledger.as<double>(), kLedgerSlots)) ||
+      (s = to_host(c, st, p->stats.as<unsigned long long>(), kStatSlots)))
+    return s;
+  uint64_t sum = fnv1a(&h, sizeof h);
+  sum = fnv1a(tal.data(), tal.size() * 8, sum);
+  sum = fnv1a(org.data(), org.size() * 8, sum);
+  sum = fnv1a(led.data(), led.size() * 8, sum);
+  sum = fnv1a(st.data(), st.size() * 8, sum);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(c, NMD_E_INVALID, "cannot open %s for writing", tmp.c_str());
+  bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 &&
+            std::fwrite(tal.data(), 8, tal.size(), f) == tal.size() &&
+            std::fwrite(org.data(), 8, org.size(), f) == org.size() &&
+            std::fwrite(led.data(), 8, led.size(), f) == led.size() &&
+            std::fwrite(st.data(), 8, st.size(), f) == st.size() &&
+            std::fwrite(&sum, 8, 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(c, NMD_E_INVALID, "writing %s failed", path);
+  }
+  return NMD_OK;
+}
+
+nmd_status nmd_load(nmd_ctx *c, int32_t id, const char *path) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->has_activity) return fail(c, NMD_E_STATE, "phantom %d has no activity map", id);
+  if (!path) return fail(c, NMD_E_INVALID, "path is required");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(c, NMD_E_INVALID, "cannot open %s", path);
+  CkptHeader h;
+  std::vector<double> tal, org, led(kLedgerSlots);
+  std::vector<unsigned long long> st(kStatSlots);
+  uint64_t sum = 0;
+  bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "NMDCKPT1", 8) == 0 &&
+            h.version == 1 && h.nvox == p->nvox && h.n_org == (uint32_t)p->n_org;
+  if (ok) {
+    tal.resize(h.nvox * 2);
+    org.resize((size_t)(h.n_org + 1) * 2);
+    ok = std::fread(tal.data(), 8, tal.size(), f) == tal.size() &&
+         std::fread(org.data(), 8, org.size(), f) == org.size() &&
+         std::fread(led.data(), 8, led.size(), f) == led.size() &&
+         std::fread(st.data(), 8, st.size(), f) == st.size() && std::fread(&sum, 8, 1, f) == 1;
+  }
+  std::fclose(f);
+  if (!ok) return fail(c, NMD_E_INVALID, "%s is not a checkpoint of this phantom's shape", path);
+  uint64_t chk = fnv1a(&h, sizeof h);
+  chk = fnv1a(tal.data(), tal.size() * 8, chk);
+  chk = fnv1a(org.data(), org.size() * 8, chk);
+  chk = fnv1a(led.data(), led.size() * 8, chk);
+  chk = fnv1a(st.data(), st.size() * 8, chk);
+  if (chk != sum) return fail(c, NMD_E_INVALID, "%s: checksum mismatch", path);
+  if (h.nx != p->nx || h.ny != p->ny || h.nz != p->nz || h.dx != p->dx || h.dy != p->dy ||
+      h.dz != p->dz || h.geom_hash != p->geom_hash)
+    return fail(c, NMD_E_STATE, "%s was saved from a different phantom geometry", path);
+  if (h.act_hash != p->act_hash)
+    return fail(c, NMD_E_STATE, "%s was saved with a different activity map", path);
+  if (h.organ_from > h.n_done) return fail(c, NMD_E_INVALID, "%s: inconsistent counters", path);
+  HIP_TRY(c, hipMemcpyAsync(p->tally.p, tal.data(), tal.size() * 8, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p->organ.p, org.data(), org.size() * 8, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p->ledger.p, led.data(), led.size() * 8, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p->stats.p, st.data(), st.size() * 8, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, launch_set_u64(p->n_done_dev.as<unsigned long long>(), h.n_done, c->stream));
+  if ((s = sync(c))) return s;
+  p->n_done = h.n_done;
+  p->organ_from = h.organ_from;
+  return NMD_OK;
 }
 
 nmd_status nmd_get_last_launch(nmd_ctx *c, uint32_t *chunk, uint32_t *grid_blocks) {

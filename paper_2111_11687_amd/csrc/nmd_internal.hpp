@@ -133,6 +133,11 @@ hipError_t launch_zero_bytes(void *p, uint64_t nbytes, hipStream_t s);
 hipError_t launch_advance(const PhantomDesc *desc, const RunIds &ids, unsigned long long n,
                           hipStream_t s);
 hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s);
+// dst[i] += src[i], i < n
+hipError_t launch_add_f64(double *dst, const double *src, uint64_t n, hipStream_t s);
+// run counters: dst[i] += src[i], except the largest-list slot, which takes the max
+hipError_t launch_add_stats(unsigned long long *dst, const unsigned long long *src,
+                            hipStream_t s);
 hipError_t launch_map_organ_reduce(const uint16_t *rec, uint64_t nvox, int n_org,
                                    const double *map, double *acc /* [n_org+1] */,
                                    hipStream_t s);

@@ -531,10 +531,19 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     }
     if (cnt == (uint32_t)kDepCap) {
       // list full (not reached on the phantoms here; counted): score this
-      // deposit on its own, which splits the history's square for voxel v
+      // deposit on its own, which splits the history's square for voxel v.
+      // A history past its organ slots merges its organ scores from the
+      // list, which will not hold this deposit: its organ score goes on its
+      // own too (the organ mean stays exact, its square is split likewise).
       atomicAdd(&wa.stat[11], 1ull);
       gadd(&D->tally[v].x, e);
       gadd(&D->tally[v].y, e * e);
+      const uint32_t o = r16 >> 8;
+      if ((oc_id >> 31) && o != 0u) {
+        const double q = e * wl.w[o] * s_irho[r16 & 0xFFu];
+        atomicAdd(&wl.org[o].x, q);
+        atomicAdd(&wl.org[o].y, q * q);
+      }
       return;
     }
     if (cnt >= kTier) {
@@ -1125,6 +1134,36 @@ hipError_t launch_advance(const PhantomDesc *desc, const RunIds &ids, unsigned l
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, unsigned long long v) { *p = v; }
+
+__global__ void add_f64_kernel(double *__restrict__ dst, const double *__restrict__ src,
+                               uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] += src[i];
+}
+
+hipError_t launch_add_f64(double *dst, const double *src, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(add_f64_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+__global__ void add_stats_kernel(unsigned long long *dst, const unsigned long long *src) {
+  const int i = threadIdx.x;
+  if (i >= kStatN) return;
+  if (i == NMD_STAT_MAX_MERGED)
+    dst[i] = src[i] > dst[i] ? src[i] : dst[i];
+  else
+    dst[i] += src[i];
+}
+
+hipError_t launch_add_stats(unsigned long long *dst, const unsigned long long *src,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(add_stats_kernel, dim3(1), dim3(64), 0, s, dst, src);
+  return hipGetLastError();
+}
 
 hipError_t launch_set_u64(unsigned long long *p, unsigned long long v, hipStream_t s) {
   hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(1), 0, s, p, v);

@@ -38,7 +38,7 @@ def test_finalize_and_organ_reduce_on_synthetic_tallies(engine, orc):
     assert np.allclose(gd, od, rtol=1e-13, atol=0)
     assert np.allclose(ge, oe, rtol=1e-12, atol=1e-300)
     assert np.array_equal(gd == 0, od == 0)
-    r, e3, _ = engine.organs(30)
+    r, e3, _ = engine.organs(30, sigma=False)
     orr, oe3 = orc.organ_stats(ph, od, oe)
     assert np.allclose(r, orr, rtol=1e-12, atol=0)
     assert np.allclose(e3, oe3, rtol=1e-12, atol=0)
@@ -106,13 +106,118 @@ def test_batched_launch_equals_separate_launches():
         eng.close()
 
 
-def test_abort_hook(engine):
+def _full(engine, pid, n_organs):
+    """Everything a run changes: tallies, counters, ledger, organ sums."""
+    s = _state(engine, pid)
+    r, e3, sig = engine.organs(pid)
+    return s + (r, e3, sig, B.nmd_get_organ_score(engine.ctx, pid, n_organs))
+
+
+def _same_full(a, b, exact=False):
+    if exact:
+        # the sums themselves bit for bit; the organ reduction of Eq. 2 and
+        # Eq. 3 runs again, with its FP64 atomics in another order
+        assert a[2] == b[2] and a[3] == b[3] and a[4] == b[4]
+        for i in (0, 1, 7, 8):
+            assert np.array_equal(a[i], b[i])
+        for i in (5, 6):
+            assert np.allclose(a[i], b[i], rtol=1e-13, atol=0)
+        return
+    _same(a[:5], b[:5])
+    for x, y in zip(a[5:], b[5:]):
+        assert np.allclose(x, y, rtol=1e-10, atol=0)
+
+
+def test_abort_hook_leaves_the_phantom_unchanged(engine):
+    """A run stopped by the abort hook returns NMD_E_ABORTED and leaves the
+    tallies, organ sums, ledger, counters and history count exactly as they
+    were; the next run then continues the streams as if it never happened."""
     prob = _small()
     engine.set_problem(33, prob)
+    engine.run(33, 200_000, 3)
+    before = _full(engine, 33, prob.n_organs)
     with pytest.raises(B.NmdError) as ei:
         engine.run(33, 10 ** 6, 3, chunk=1000, abort_after_chunks=5)
     assert ei.value.status == -6
-    assert engine.stats(33)["histories"] < 10 ** 6
+    _same_full(_full(engine, 33, prob.n_organs), before, exact=True)
+    # an armed hook that does not fire commits the run like a plain one
+    engine.run(33, 100_000, 3, chunk=1000, abort_after_chunks=10 ** 6)
+    engine.run(33, 100_000, 3)
+    got = _full(engine, 33, prob.n_organs)
+    engine.set_problem(33, prob)  # the phantom id is part of the streams
+    engine.run(33, 400_000, 3)
+    _same_full(got, _full(engine, 33, prob.n_organs))
+
+
+def test_set_tallies_voids_the_organ_sigma(engine):
+    """Voxel sums restored by nmd_set_tallies keep Eq. 1-3 available, but the
+    per-history organ sums no longer cover the N histories: the organ-mean
+    sigma and the organ score are refused rather than divided by the wrong N."""
+    prob = _small()
+    engine.set_problem(35, prob)
+    engine.run(35, 100_000, 4)
+    r0, e0, _ = engine.organs(35)
+    s, s2, n = engine.tallies(35)
+    B.nmd_set_tallies(engine.ctx, 35, s, s2, n)
+    r1, e1, _ = engine.organs(35, sigma=False)
+    assert np.allclose(r1, r0, rtol=1e-13, atol=0) and np.allclose(e1, e0, rtol=1e-12, atol=0)
+    for fn in (lambda: engine.organs(35),
+               lambda: B.nmd_get_organ_score(engine.ctx, 35, prob.n_organs)):
+        with pytest.raises(B.NmdError) as ei:
+            fn()
+        assert ei.value.status == -3
+    B.nmd_reset_tallies(engine.ctx, 35)
+    engine.run(35, 1000, 4)
+    engine.organs(35)  # covered again after a reset
+
+
+def test_save_load_equals_one_long_run(engine, tmp_path):
+    """Save after N1 histories, load into the phantom registered afresh, run N2
+    more with the same seed: tallies, organ rates, organ sigma, ledger and
+    counters equal one run of N1 + N2 (up to the order of FP64 atomics)."""
+    prob = _small()
+    path = str(tmp_path / "ckpt.nmd")
+    engine.set_problem(36, prob)
+    engine.run(36, 150_000, 6)
+    B.nmd_save(engine.ctx, 36, path)
+    # a fresh registration of the same id (its random streams are keyed by
+    # the id), restored from the file
+    engine.set_problem(36, prob)
+    B.nmd_load(engine.ctx, 36, path)
+    engine.run(36, 250_000, 6)
+    got = _full(engine, 36, prob.n_organs)
+    engine.set_problem(36, prob)
+    engine.run(36, 400_000, 6)
+    ref = _full(engine, 36, prob.n_organs)
+    _same_full(got, ref)
+    assert got[2] == 400_000 and (got[7] > 0).sum() >= 20  # the organs this phantom holds
+
+
+def test_load_rejects_other_phantoms_and_damaged_files(engine, tmp_path):
+    prob = _small()
+    path = str(tmp_path / "ckpt.nmd")
+    engine.set_problem(38, prob)
+    engine.run(38, 50_000, 7)
+    B.nmd_save(engine.ctx, 38, path)
+    before = _full(engine, 38, prob.n_organs)
+
+    def status(*a):
+        with pytest.raises(B.NmdError) as ei:
+            B.nmd_load(engine.ctx, *a)
+        return ei.value.status
+
+    other = _small(seed=10)  # same shape, other organs and activity
+    engine.set_problem(39, other)
+    assert status(39, path) == -3
+    raw = bytearray(open(path, "rb").read())
+    raw[len(raw) // 2] ^= 0x40
+    bad = str(tmp_path / "bad.nmd")
+    open(bad, "wb").write(bytes(raw))
+    assert status(38, bad) == -1
+    open(bad, "wb").write(bytes(raw[:1000]))
+    assert status(38, bad) == -1
+    assert status(38, str(tmp_path / "missing.nmd")) == -1
+    _same_full(_full(engine, 38, prob.n_organs), before, exact=True)
 
 
 def test_error_paths(engine):
