@@ -26,30 +26,74 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Ideal (non-divergent) VALU instruction counts per unit of work of the
-# transport kernel, counted in its gfx950 code paths; multiplied by the run's
-# own workload counters they give the algorithmic VALU lane-operations.
-VALU_PER_PHILOX_BLOCK = 100   # 10 rounds: 2 mul_lo, 2 mul_hi, 4 xor, 2 mov
-VALU_PER_UNIFORM = 10         # word select, shift, convert, scale
-VALU_PER_STEP = 43            # free flight, inside test, voxel index, event choice
-VALU_PER_COMPTON = 192        # KN attempt 83 + rotation 62 + energy update 47
-VALU_PER_RAYLEIGH = 92        # Thomson inversion 30 + rotation 62
-VALU_PER_HISTORY = 60         # alias sample, voxel coordinates, photon starts
-VALU_PER_MERGED = 20          # tally and organ flush per distinct voxel
-# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: one lane-operation per lane per cycle
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# Bytes moved beyond L2 per decay by the transport kernel on the patient
-# phantom: FETCH_SIZE x 2 + WRITE_SIZE of rocprofv3 --pmc runs, scaled
-# against a profiled 256 MiB copy (profiles/transport_patient256x256x320_counters.md).
-TRANSPORT_TRAFFIC_BYTES_PER_DECAY = 1769.0
+# VALU instructions per unit of the transport's work on a non-divergent
+# wave, measured with the probe kernels unit_kernel<K> (SQ_INSTS_VALU per
+# dispatch, profiles/transport_units_counters.md); multiplied by the run's
+# own per-decay counters they give the algorithmic VALU lane-operations.
+VALU_PER_PHILOX_BLOCK = 53
+VALU_PER_UNIFORM = 4
+VALU_PER_STEP = 34      # free flight, inside test, voxel index, record gather, event choice
+VALU_PER_COMPTON = 193  # one Klein-Nishina attempt, azimuth, rotation, energy factors
+VALU_PER_RAYLEIGH = 106  # Thomson angle and rotation
+VALU_PER_HISTORY = 40   # alias voxel, position in the voxel, one Marsaglia attempt
+VALU_PER_MERGED = 10    # tally address, e^2; the two FP64 atomics are counted apart
+# FP32 vector peak 157.3 TFLOP/s = 78.6 T FMA lane-operations/s (256 CUs x
+# 128 lanes x 2.4 GHz); a non-packed v_fmamk_f32 loop reaches 60.0 T/s
+# (profiles/ceilings_mi355x.md), so the peak is not a packed-only figure.
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
+HBM_PEAK = 8.0e12  # bytes/s
+# Bytes moved beyond L2 per decay by the transport kernel: FETCH_SIZE x 2 +
+# WRITE_SIZE of rocprofv3 --pmc runs, scaled against a profiled 256 MiB copy
+# (profiles/transport_patient256x256x320_counters.md).  Only workloads whose
+# counters were taken with the current kernel have an entry.
+TRAFFIC_BYTES_PER_DECAY = {"patient": 1769.0}
 
 
 def valu_ops(stats):
+    """Algorithmic VALU lane-operations per decay from per-decay counters."""
     blocks = stats["rng_blocks"]
     return (blocks * VALU_PER_PHILOX_BLOCK + 4 * blocks * VALU_PER_UNIFORM
             + stats["steps"] * VALU_PER_STEP + stats["compton"] * VALU_PER_COMPTON
             + stats["rayleigh"] * VALU_PER_RAYLEIGH + stats["histories"] * VALU_PER_HISTORY
             + stats["merged"] * VALU_PER_MERGED)
+
+
+def hbm_bytes(stats):
+    """Algorithmic HBM bytes per decay: one 16-byte alias entry per history,
+    one 2-byte voxel record per Woodcock step and a 16-byte read plus a
+    16-byte write of the (S, S2) tally pair per merged deposit."""
+    return 16.0 * stats["histories"] + 2.0 * stats["steps"] + 32.0 * stats["merged"]
+
+
+def measure_atomic_ceiling(ctx):
+    """FP64 atomic adds/s at scattered addresses of a 256 MiB table (the
+    patient's tally is 320 MiB), measured on this device before the timed
+    region."""
+    from paper_2111_11687_amd import binding as B
+    return B.nmd_probe_ceiling(ctx, "atomic_f64", 256 << 20, 5)[0]
+
+
+def transport_roofline(per_decay, nd, kern_ms, traffic_per_decay, atomic_ceiling):
+    """Roofline of one transport launch of nd decays lasting kern_ms.  Its
+    binding ceiling is the FP64 atomic rate: two atomics (S and S2) per
+    merged deposit; the VALU and HBM terms are reported beside it."""
+    ops, byt = valu_ops(per_decay), hbm_bytes(per_decay)
+    atom = 2.0 * per_decay["merged"]
+    sec = kern_ms * 1e-3
+    achieved = atom * nd / sec
+    return {"bound": "atomic", "achieved": achieved / 1e9, "peak": atomic_ceiling / 1e9,
+            "unit": "G FP64 atomics/s", "frac": achieved / atomic_ceiling,
+            "peak_source": "measured on this device: scattered FP64 atomic adds, 256 MiB table",
+            "traffic": None if traffic_per_decay is None else traffic_per_decay * nd,
+            "traffic_unit": "bytes beyond L2 per launch (profiled)",
+            "kernel": "transport_kernel", "kernel_ms": kern_ms,
+            "atomics_per_decay": atom,
+            "valu": {"ops_per_decay": ops, "achieved_tops": ops * nd / sec / 1e12,
+                     "peak_tops": VALU_PEAK_OPS / 1e12,
+                     "frac": ops * nd / sec / VALU_PEAK_OPS},
+            "hbm": {"algorithmic_bytes_per_decay": byt,
+                    "achieved_gbs": byt * nd / sec / 1e9,
+                    "frac": byt * nd / sec / HBM_PEAK}}
 
 
 def cpu_baseline(prob, target_s):
@@ -63,15 +107,15 @@ def cpu_baseline(prob, target_s):
     times = []
     for n0 in (50000, 150000):
         t0 = time.perf_counter()
-        oracle.run(ph, n0, 7, n_threads=threads)
+        oracle.run(ph, n0, 7, n_threads=threads, photons_per_decay=prob.photons_per_decay)
         times.append(time.perf_counter() - t0)
     per = max((times[1] - times[0]) / 100000, 1e-9)
     n = int(max(150000, min(5e7, target_s / per)))
     t0 = time.perf_counter()
-    tal, _ = oracle.run(ph, n, 8, n_threads=threads)
+    tal, _ = oracle.run(ph, n, 8, n_threads=threads, photons_per_decay=prob.photons_per_decay)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
-            "sample": "%d decays of the same phantom, exact-traversal FP64 oracle, %.1f s"
+            "sample": "%d histories of the same phantom, exact-traversal FP64 oracle, %.1f s"
                       % (n, dt)}
 
 
@@ -80,17 +124,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--decays-per-step", type=int, default=10 ** 8)
+    ap.add_argument("--decays-per-step", type=int, default=0,
+                    help="decays (histories) per step; 0 = the workload's own")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("patient", "batch64", "denoiser", "organ-time", "ingest"),
+    ap.add_argument("--workload", choices=("patient", "slab", "water", "paper101", "batch64",
+                                           "denoiser", "organ-time", "ingest", "ceilings",
+                                           "units"),
                     default="patient",
-                    help="patient: the 256x256x320 phantom (the headline metric); batch64: 64 "
+                    help="patient: the 256x256x320 phantom (the headline metric); slab, water, "
+                         "paper101: the other plain MC phantoms; batch64: 64 "
                          "uneven phantoms, 10^7 decays each per step, one graph-captured "
                          "launch per step with the autotuned chunk; denoiser: U-Net training "
                          "steps on 128x128x160 boxes and inference on the whole phantom; "
                          "organ-time: time to <=1%% organ dose, plain MC vs MC + trained "
-                         "denoiser with the MC judge and fallback, on held-out patients")
+                         "denoiser with the MC judge and fallback, on held-out patients; "
+                         "ceilings: measured HBM, atomic, gather, VALU and MFMA rates; units: "
+                         "the per-unit probe kernels of the VALU work model (profile them "
+                         "with rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES)")
     ap.add_argument("--phantoms", type=int, default=2,
                     help="organ-time: held-out patients (seeds 20008 onward)")
     ap.add_argument("--weights", default=None,
@@ -122,19 +173,60 @@ def main():
         return bench_ingest(args)
     if args.workload == "organ-time":
         return bench_organ_time(args)
-    prob = P.patient_phantom()
+    if args.workload == "ceilings":
+        return bench_ceilings(args)
+    if args.workload == "units":
+        return bench_units(args)
+    return bench_mc(args)
+
+
+# The plain Monte Carlo workloads: phantom, photons per decay (history), the
+# decays of one step and the seed of the transport streams.
+MC_WORKLOADS = {
+    "patient": ("patient phantom 256x256x320 voxels 2x2x3 mm, 27 organs, lognormal FDG-like "
+                "activity, 2 photons per decay", 10 ** 8, 103),
+    "slab": ("slab phantom 128^3 voxels of 3 mm: soft-tissue block in air with a lung slab and "
+             "a bone cylinder, point source of photon pairs at the centre", 10 ** 8, 102),
+    "water": ("water cube 64^3 voxels of 2 mm, isotropic point source of single 0.511 MeV "
+              "photons at voxel (32,32,32), 10^6 histories per job", 10 ** 6, 1),
+    "paper101": ("water cube 101^3 voxels of 0.5 mm (the paper's point-source geometry), "
+                 "single 0.511 MeV photons from the centre voxel, 10^8 histories per job",
+                 10 ** 8, 11),
+}
+
+
+def mc_problem(name):
+    from paper_2111_11687_amd import phantoms as P
+    if name == "patient":
+        return P.patient_phantom()
+    if name == "slab":
+        return P.slab_phantom()
+    if name == "water":
+        return P.water_point_source(n=64, voxel_mm=2.0)
+    return P.water_point_source(n=101, voxel_mm=0.5, seed=11)
+
+
+def bench_mc(args):
+    """One step = nmd_run_histories over one batch of decays, then the Eq. 1
+    maps (nmd_get_dose) and the organ reduction (nmd_get_organ_dose)."""
+    import torch
+    from paper_2111_11687_amd import binding as B
+
+    what, nd_default, seed = MC_WORKLOADS[args.workload]
+    prob = mc_problem(args.workload)
     eng = B.Engine(0)
     eng.set_problem(0, prob)
+    opts = B.nmd_run_opts_default()
+    opts.photons_per_decay = prob.photons_per_decay
     stream = torch.cuda.current_stream()
     rate = torch.empty(prob.shape, dtype=torch.float64, device="cuda")
     rel = torch.empty_like(rate)
-    nd = args.decays_per_step
-    seed = 103
+    nd = args.decays_per_step or nd_default
 
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        B.nmd_run_histories(eng.ctx, 0, nd, seed, None)
+        B.nmd_run_histories(eng.ctx, 0, nd, seed, opts)
         if ev is not None:
             ev[1].record(stream)
         B.nmd_get_dose(eng.ctx, 0, rate, rel)
@@ -143,6 +235,7 @@ def main():
     for _ in range(args.warmup):
         step()
     B.nmd_reset_tallies(eng.ctx, 0)
+    atomic_ceiling = measure_atomic_ceiling(eng.ctx)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
@@ -156,9 +249,6 @@ def main():
     led = eng.ledger(0)
     total = args.steps * nd
     value = total / dt
-
-    ops_launch = valu_ops(stats) / args.steps
-    achieved = ops_launch / (kern_ms * 1e-3)
     dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"]
     balance = (dep + led["escaped"] + led["discarded"]) / led["emitted"] - 1.0
     print(json.dumps({"steps_ms": [round(a.elapsed_time(b), 3) for a, b in evs],
@@ -166,8 +256,10 @@ def main():
                       "ledger_balance": balance,
                       "organ_rate_gy_s": organs[0][:5].tolist(),
                       "organ_rel_sigma": organs[2][:5].tolist()}), file=sys.stderr)
+    per_decay = {k: v / total for k, v in stats.items()}
     out = {
-        "metric": "histories/s (10^9-decay phantom)",
+        "metric": "histories/s (10^9-decay phantom)" if args.workload == "patient"
+        else "histories/s",
         "value": value,
         "unit": "histories/s",
         "n_gpus": 1,
@@ -179,20 +271,76 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "patient phantom 256x256x320 voxels 2x2x3 mm, 27 organs, "
-                               "lognormal FDG-like activity, 2 photons per decay",
-                   "decays_per_step": nd, "decays_per_job": total,
+        "config": {"workload": what, "decays_per_step": nd, "decays_per_job": total,
+                   "photons_per_decay": prob.photons_per_decay,
                    "tally": "f64", "transport": "f32"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
-                     "traffic": TRANSPORT_TRAFFIC_BYTES_PER_DECAY * nd,
-                     "traffic_unit": "bytes beyond L2 per launch (profiled)",
-                     "kernel": "transport_kernel", "kernel_ms": kern_ms,
-                     "ops_per_decay": ops_launch / nd},
+        "roofline": transport_roofline(per_decay, nd, kern_ms,
+                                       TRAFFIC_BYTES_PER_DECAY.get(args.workload),
+                                       atomic_ceiling),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     eng.close()
+    print(json.dumps(out), flush=True)
+
+
+# Sizes of the measured ceilings: tallies of the water cube (4 MiB), the slab
+# (32 MiB) and the patient (320 MiB, bracketed by 256 and 512 MiB); record
+# arrays of the slab (4 MiB) and the patient (42 MB, bracketed by 32 and
+# 64 MiB).
+CEILING_RUNS = (("copy", 1 << 30), ("atomic_f64", 4 << 20), ("atomic_f64", 32 << 20),
+                ("atomic_f64", 256 << 20), ("atomic_f64", 512 << 20),
+                ("gather_u16", 4 << 20), ("gather_u16", 32 << 20), ("gather_u16", 64 << 20),
+                ("valu_fma", 0), ("mul64", 0), ("mfma_bf16", 0))
+
+
+def bench_ceilings(args):
+    """Measured rates of the hardware paths the transport uses (HIP-event
+    timed probe kernels); value = the stream-copy bandwidth."""
+    from paper_2111_11687_amd import binding as B
+    eng = B.Engine(0)
+    res = {}
+    t0 = time.perf_counter()
+    for kind, nbytes in CEILING_RUNS:
+        rate, ms = B.nmd_probe_ceiling(eng.ctx, kind, nbytes, max(args.steps, 1))
+        key = kind if not nbytes or kind == "copy" else "%s_%dMiB" % (kind, nbytes >> 20)
+        res[key] = {"rate": rate, "ms": ms}
+        print(json.dumps({key: res[key]}), file=sys.stderr, flush=True)
+    dt = time.perf_counter() - t0
+    eng.close()
+    units = {"copy": "bytes/s", "atomic_f64": "atomics/s", "gather_u16": "loads/s",
+             "valu_fma": "lane-ops/s", "mul64": "lane-ops/s", "mfma_bf16": "FLOP/s"}
+    out = {"metric": "measured ceilings (HBM copy bandwidth)",
+           "value": res["copy"]["rate"] / 1e9, "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": dt * 1e3 / max(args.steps, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "probe kernels: 1 GiB copy, FP64 atomics and 2-byte gathers "
+                                  "at scattered addresses of tally- and record-sized arrays, "
+                                  "FP32 FMA, 32x32->64 multiply and BF16 MFMA loops",
+                      "rates": {k: v["rate"] for k, v in res.items()},
+                      "rate_units": units}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_units(args):
+    """One dispatch of each unit probe (8192 workgroups x 256 lanes x 256
+    iterations); their SQ_INSTS_VALU counters give the VALU model."""
+    from paper_2111_11687_amd import binding as B
+    eng = B.Engine(0)
+    iters, blocks = 256, 8192
+    ms = {}
+    for k in B.UNITS:
+        B.nmd_probe_unit(eng.ctx, k, 8, 64)  # warm-up
+        ms[k] = B.nmd_probe_unit(eng.ctx, k, iters, blocks)
+        print(json.dumps({k: ms[k]}), file=sys.stderr, flush=True)
+    eng.close()
+    out = {"metric": "unit probe launch time", "value": sum(ms.values()), "unit": "ms",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": sum(ms.values()),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "unit_kernel<0..7>: %d workgroups x 256 lanes x %d units"
+                                  % (blocks, iters), "launch_ms": ms}}
     print(json.dumps(out), flush=True)
 
 
@@ -369,7 +517,6 @@ def bench_denoiser(args):
 # (profiles/denoiser_conv_box160x128x128_counters.md)
 DENOISER_DOM_TRAFFIC_BYTES = (57974.7 * 2 + 81920.0) * 1024
 
-HBM_PEAK = 8.0e12  # bytes/s
 # HBM bytes of one ingest_kernel launch on the benchmark's CT: FETCH_SIZE x 2
 # + WRITE_SIZE of rocprofv3 --pmc runs scaled against a profiled 256 MiB copy
 # (profiles/ingest_ct512x512x438_to_patient256x256x320.md)

@@ -56,6 +56,11 @@ NN_EXPORTS = ("nmd_conv3d_fwd", "nmd_conv3d_bwd_data", "nmd_conv3d_bwd_weight", 
 
 INGEST_EXPORTS = ("nmd_resample_linear", "nmd_ct_to_phantom", "nmd_ct_ingest")
 
+PROBE_EXPORTS = ("nmd_probe_ceiling", "nmd_probe_unit")
+CEILINGS = {"copy": 0, "atomic_f64": 1, "gather_u16": 2, "valu_fma": 3, "mul64": 4,
+            "mfma_bf16": 5}
+UNITS = ("loop", "philox", "uniform", "step", "compton", "rayleigh", "history", "merged")
+
 
 class nmd_grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("spacing_mm", ctypes.c_float * 3),
@@ -75,7 +80,8 @@ EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_get_ledger", "nmd_get_run_stats", "nmd_get_tallies", "nmd_set_tallies",
            "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
            "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
-           "nmd_graph_launch", "nmd_graph_destroy") + NN_EXPORTS + INGEST_EXPORTS
+           "nmd_graph_launch", "nmd_graph_destroy", "nmd_save", "nmd_load") + NN_EXPORTS + INGEST_EXPORTS + \
+    PROBE_EXPORTS
 
 _lib = None
 
@@ -117,6 +123,8 @@ def load_library(path: str = LIB_PATH):
         "nmd_graph_create": [vp, i32, u64, u64, ctypes.POINTER(nmd_run_opts), vp, vp,
                              ctypes.POINTER(vp)],
         "nmd_graph_launch": [vp],
+        "nmd_save": [vp, i32, ctypes.c_char_p],
+        "nmd_load": [vp, i32, ctypes.c_char_p],
         "nmd_graph_destroy": [vp],
         "nmd_conv3d_fwd": [vp, i32, i32, i32, i32, ctypes.POINTER(nmd_nn_src), vp, vp, i32, i32,
                            vp, vp],
@@ -139,6 +147,9 @@ def load_library(path: str = LIB_PATH):
         "nmd_ct_to_phantom": [vp, vp, ctypes.c_int64, ctypes.POINTER(nmd_ct_table), vp, vp],
         "nmd_ct_ingest": [vp, vp, ctypes.POINTER(nmd_grid), ctypes.POINTER(nmd_grid),
                           ctypes.POINTER(nmd_ct_table), vp, vp],
+        "nmd_probe_ceiling": [vp, i32, u64, ctypes.c_uint32, ctypes.POINTER(d),
+                              ctypes.POINTER(d)],
+        "nmd_probe_unit": [vp, i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(d)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -232,27 +243,36 @@ def nmd_get_dose(ctx, phantom_id, dose_rate, rel_uncertainty=None):
                                             _dptr(rel_uncertainty)))
 
 
-def nmd_get_organ_dose(ctx, phantom_id, n_organs):
+def nmd_get_organ_dose(ctx, phantom_id, n_organs, sigma=True):
     """Returns (Eq. 2 dose rate, Eq. 3 uncertainty, relative sigma of the
-    organ mean) as float64 numpy arrays of n_organs."""
+    organ mean, or None with sigma=False) as float64 numpy arrays of
+    n_organs."""
     r = np.zeros(n_organs)
     e = np.zeros(n_organs)
-    s = np.zeros(n_organs)
-    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    s = np.zeros(n_organs) if sigma else None
+    p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
     _check(ctx, load_library().nmd_get_organ_dose(ctx, int(phantom_id), int(n_organs), p(r),
                                                   p(e), p(s)))
     return r, e, s
 
 
-def nmd_read_organ_dose(ctx, phantom_id, n_organs):
+def nmd_read_organ_dose(ctx, phantom_id, n_organs, sigma=True):
     """Results of the last organ reduction (e.g. one a graph ran)."""
     r = np.zeros(n_organs)
     e = np.zeros(n_organs)
-    s = np.zeros(n_organs)
-    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    s = np.zeros(n_organs) if sigma else None
+    p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
     _check(ctx, load_library().nmd_read_organ_dose(ctx, int(phantom_id), int(n_organs), p(r),
                                                    p(e), p(s)))
     return r, e, s
+
+
+def nmd_save(ctx, phantom_id, path):
+    _check(ctx, load_library().nmd_save(ctx, int(phantom_id), os.fsencode(path)))
+
+
+def nmd_load(ctx, phantom_id, path):
+    _check(ctx, load_library().nmd_load(ctx, int(phantom_id), os.fsencode(path)))
 
 
 def nmd_get_last_launch(ctx):
@@ -423,6 +443,23 @@ def nmd_organ_mean_map(ctx, phantom_id, dose_map, n_organs):
     return out
 
 
+def nmd_probe_ceiling(ctx, kind, nbytes=0, repeats=10):
+    """(rate, ms) of ceiling `kind` (a CEILINGS name or number)."""
+    k = CEILINGS[kind] if isinstance(kind, str) else int(kind)
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, load_library().nmd_probe_ceiling(ctx, k, nbytes, repeats, ctypes.byref(rate),
+                                                 ctypes.byref(ms)))
+    return rate.value, ms.value
+
+
+def nmd_probe_unit(ctx, kind, iters, blocks):
+    """Launch time (ms) of the unit probe `kind` (a UNITS name or number)."""
+    k = UNITS.index(kind) if isinstance(kind, str) else int(kind)
+    ms = ctypes.c_double()
+    _check(ctx, load_library().nmd_probe_unit(ctx, k, iters, blocks, ctypes.byref(ms)))
+    return ms.value
+
+
 def make_grid(g):
     """nmd_grid from a dict n=(nx, ny, nz), spacing=(sx, sy, sz), origin=(ox, oy, oz) (mm)."""
     out = nmd_grid()
@@ -540,8 +577,9 @@ class Engine:
         n = nmd_get_tallies(self.ctx, phantom_id, s, s2)
         return s, s2, n
 
-    def organs(self, phantom_id):
-        return nmd_get_organ_dose(self.ctx, phantom_id, self.problems[phantom_id].n_organs)
+    def organs(self, phantom_id, sigma=True):
+        return nmd_get_organ_dose(self.ctx, phantom_id, self.problems[phantom_id].n_organs,
+                                  sigma)
 
     def ledger(self, phantom_id):
         return nmd_get_ledger(self.ctx, phantom_id)

@@ -8,9 +8,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, f)
-           for f in ("nmd_kernels.hip", "nmd_api.hip", "nmd_nn.hip", "nmd_ingest.hip")]
+           for f in ("nmd_kernels.hip", "nmd_api.hip", "nmd_nn.hip", "nmd_ingest.hip",
+                     "nmd_probe.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("nmd_internal.hpp", "nmd_device.hpp")] + [
-    os.path.join(HERE, "..", "include", f) for f in ("nmdose.h", "nmdose_nn.h", "nmdose_ingest.h")]
+    os.path.join(HERE, "..", "include", f) for f in ("nmdose.h", "nmdose_nn.h", "nmdose_ingest.h",
+                                                  "nmdose_probe.h")]
 LIB = os.path.join(HERE, "libnmdose.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -25,21 +27,42 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into one shared library; always recompiles."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass warns that it does not know the packed-fp32 feature
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
-    if err.strip() and verbose:
-        print(err, file=sys.stderr)
-    os.replace(tmp, LIB)
+    return res.returncode, err
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source (in parallel) and link one shared library;
+    always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(CSRC, os.path.basename(src) + ".o" + tag) for src in SOURCES]
+    cmds = [[HIPCC] + [f for f in FLAGS if f not in ("-shared",) and not f.startswith("-Wl,")]
+            + ["-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    try:
+        with ThreadPoolExecutor(max_workers=min(len(cmds), 8)) as ex:
+            results = list(ex.map(_run, cmds))
+        for cmd, (rc, err) in zip(cmds, results):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            if rc != 0:
+                raise RuntimeError("hipcc failed:\n" + err)
+            if err.strip() and verbose:
+                print(err, file=sys.stderr)
+        tmp = LIB + ".tmp" + tag
+        rc, err = _run([HIPCC] + FLAGS + ["-o", tmp] + objs)
+        if rc != 0:
+            raise RuntimeError("hipcc link failed:\n" + err)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

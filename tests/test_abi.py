@@ -1,5 +1,6 @@
 """The C ABI library loads on a machine without a GPU and exports every
-entry point include/nmdose.h, include/nmdose_nn.h and include/nmdose_ingest.h
+entry point include/nmdose.h, include/nmdose_nn.h, include/nmdose_ingest.h and
+include/nmdose_probe.h
 declare; calls without a device fail with a status instead of crashing."""
 import ctypes
 import os
@@ -9,7 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", f)
-           for f in ("nmdose.h", "nmdose_nn.h", "nmdose_ingest.h")]
+           for f in ("nmdose.h", "nmdose_nn.h", "nmdose_ingest.h", "nmdose_probe.h")]
 LIB = os.path.join(ROOT, "paper_2111_11687_amd", "libnmdose.so")
 
 
