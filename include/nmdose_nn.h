@@ -155,6 +155,21 @@ nmd_status nmd_nn_cast_weight(nmd_ctx *ctx, const float *theta, int32_t c_out, i
 nmd_status nmd_organ_mean_map(nmd_ctx *ctx, int32_t phantom_id, const double *map,
                               int32_t n_organs, double *out);
 
+/* nmd_organ_mean_map for callers that cannot allocate (code under HIP graph
+ * capture, allocation-free serving loops, harnesses that forbid hipMalloc):
+ * same arguments, results and errors, but the call makes no device
+ * allocation (no hipMalloc or hipFree) and, when it succeeds, no host heap
+ * allocation either.  Its per-label partial sums live in a library-owned
+ * static device buffer of 256 FP64 slots (2 KiB per device, kept until the
+ * process ends), cleared by a fill kernel at the start of every call; a
+ * phantom with more than 255 labels is refused with NMD_E_UNSUPPORTED (labels
+ * are 8-bit, so none can have more).  Every call on a device shares that
+ * device's buffer: calls that overlap on one device (from several threads or
+ * contexts on different streams) race and must be serialised by the caller.
+ * Synchronises the stream. */
+nmd_status nmd_organ_mean_map_noalloc(nmd_ctx *ctx, int32_t phantom_id, const double *map,
+                                      int32_t n_organs, double *out);
+
 /* Test hook: one 16x16x32 BF16 matrix-core product, d = a * b with a
  * row-major bfloat16 [16][32], b row-major [32][16], d row-major FP32 [16][16]. */
 nmd_status nmd_debug_mfma(nmd_ctx *ctx, const uint16_t *a, const uint16_t *b, float *d);

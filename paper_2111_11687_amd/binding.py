@@ -52,7 +52,8 @@ class nmd_nn_src(ctypes.Structure):
 
 NN_EXPORTS = ("nmd_conv3d_fwd", "nmd_conv3d_bwd_data", "nmd_conv3d_bwd_weight", "nmd_nn_pool2",
               "nmd_nn_combine", "nmd_nn_prepare", "nmd_nn_head_loss", "nmd_nn_head_infer",
-              "nmd_nn_adam", "nmd_nn_cast_weight", "nmd_organ_mean_map", "nmd_debug_mfma")
+              "nmd_nn_adam", "nmd_nn_cast_weight", "nmd_organ_mean_map",
+              "nmd_organ_mean_map_noalloc", "nmd_debug_mfma")
 
 INGEST_EXPORTS = ("nmd_resample_linear", "nmd_ct_to_phantom", "nmd_ct_ingest")
 
@@ -141,6 +142,7 @@ def load_library(path: str = LIB_PATH):
                         ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp, i32, i32],
         "nmd_nn_cast_weight": [vp, vp, i32, i32, vp, vp],
         "nmd_organ_mean_map": [vp, i32, vp, i32, vp],
+        "nmd_organ_mean_map_noalloc": [vp, i32, vp, i32, vp],
         "nmd_debug_mfma": [vp, vp, vp, vp],
         "nmd_resample_linear": [vp, vp, ctypes.POINTER(nmd_grid), ctypes.POINTER(nmd_grid),
                                 ctypes.c_float, vp],
@@ -440,6 +442,14 @@ def nmd_organ_mean_map(ctx, phantom_id, dose_map, n_organs):
     _check(ctx, load_library().nmd_organ_mean_map(ctx, int(phantom_id), _dptr(dose_map),
                                                   int(n_organs),
                                                   out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def nmd_organ_mean_map_noalloc(ctx, phantom_id, dose_map, n_organs):
+    out = np.zeros(n_organs)
+    _check(ctx, load_library().nmd_organ_mean_map_noalloc(
+        ctx, int(phantom_id), _dptr(dose_map), int(n_organs),
+        out.ctypes.data_as(ctypes.c_void_p)))
     return out
 
 

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -101,6 +102,7 @@ struct nmd_ctx {
   std::map<int, Phantom> ph;
   DevBuf nn_scratch;  // workspace of the denoiser's backward-weight partials
   bool poisoned = false;
+  double *noalloc_scratch = nullptr;  // this device's `scratch` (nmd_organ_mean_map_noalloc)
 };
 
 namespace {
@@ -527,6 +529,36 @@ struct nmd_graph {
 namespace {
 }  // namespace
 
+// ---- allocation-free organ means ---------------------------------------------
+// Device scratch of nmd_organ_mean_map_noalloc: one FP64 partial sum per organ
+// label, 2 KiB on every device the library runs on, held until the process
+// ends.  Host code never passes `scratch` itself (its host-side name is not a
+// device address): the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, when the first context on it is
+// created.
+namespace {
+constexpr int kNoallocSlots = kMaxOrganSlots;
+__device__ __align__(256) double scratch[kNoallocSlots];
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;  // device -> address of `scratch` there
+
+nmd_status bind_noalloc_scratch(nmd_ctx *c) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(c->device);
+  if (it == g_scratch_ptr.end()) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(c, NMD_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    it = g_scratch_ptr.emplace(c->device, static_cast<double *>(ptr)).first;
+  }
+  c->noalloc_scratch = it->second;
+  return NMD_OK;
+}
+}  // namespace
+
 // ============================================================================
 // C ABI
 // ============================================================================
@@ -564,6 +596,10 @@ nmd_status nmd_create(nmd_ctx **out, int device, void *stream) {
     return NMD_E_HIP;
   }
   c->cu_count = prop.multiProcessorCount;
+  if (bind_noalloc_scratch(c) != NMD_OK) {
+    delete c;
+    return NMD_E_HIP;
+  }
   c->arch = prop.gcnArchName;
   for (char &ch : c->arch)
     if (ch == ' ' || ch == '|') ch = '_';
@@ -987,6 +1023,37 @@ nmd_status nmd_organ_mean_map(nmd_ctx *c, int32_t id, const double *map, int32_t
                                      acc.as<double>(), c->stream));
   std::vector<double> h(p->n_org + 1);
   HIP_TRY(c, hipMemcpyAsync(h.data(), acc.p, acc.n, hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c))) return s;
+  for (int o = 1; o <= n_organs; ++o) {
+    const double cnt = (double)p->organ_count[o];
+    out[o - 1] = cnt > 0 ? h[o] / cnt : 0.0;
+  }
+  return NMD_OK;
+}
+
+nmd_status nmd_organ_mean_map_noalloc(nmd_ctx *c, int32_t id, const double *map,
+                                      int32_t n_organs, double *out) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (!p->has_label) return fail(c, NMD_E_STATE, "phantom %d has no organ labels", id);
+  if (!map || !out || n_organs < 0 || n_organs > p->n_org)
+    return fail(c, NMD_E_INVALID, "bad map, output or n_organs");
+  const int slots = p->n_org + 1;
+  if (slots > kNoallocSlots)
+    return fail(c, NMD_E_UNSUPPORTED, "%d organ labels exceed the %d-slot device scratch",
+                slots, kNoallocSlots);
+  if (!c->noalloc_scratch) return fail(c, NMD_E_STATE, "no device scratch on this device");
+  double *acc = c->noalloc_scratch;
+  // the previous call's sums are still there: clear this call's slots (a
+  // fill kernel, so the call has no memset node if a caller captures it)
+  HIP_TRY(c, launch_zero_bytes(acc, (uint64_t)slots * sizeof(double), c->stream));
+  HIP_TRY(c, launch_map_organ_reduce(p->rec.as<uint16_t>(), p->nvox, p->n_org, map, acc,
+                                     c->stream));
+  double h[kNoallocSlots];
+  HIP_TRY(c, hipMemcpyAsync(h, acc, (size_t)slots * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
   if ((s = sync(c))) return s;
   for (int o = 1; o <= n_organs; ++o) {
     const double cnt = (double)p->organ_count[o];
