@@ -142,6 +142,9 @@ def main():
                          "ceilings: measured HBM, atomic, gather, VALU and MFMA rates; units: "
                          "the per-unit probe kernels of the VALU work model (profile them "
                          "with rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES)")
+    ap.add_argument("--electrons", type=float, default=0.0, metavar="MEV",
+                    help="plain MC workloads: walk Compton electrons above this cutoff "
+                         "(Section 2.1 uses 0.2 MeV); 0 deposits them on the spot")
     ap.add_argument("--phantoms", type=int, default=2,
                     help="organ-time: held-out patients (seeds 20008 onward)")
     ap.add_argument("--weights", default=None,
@@ -211,11 +214,18 @@ def bench_mc(args):
     maps (nmd_get_dose) and the organ reduction (nmd_get_organ_dose)."""
     import torch
     from paper_2111_11687_amd import binding as B
+    from paper_2111_11687_amd import phantoms as P
 
     what, nd_default, seed = MC_WORKLOADS[args.workload]
     prob = mc_problem(args.workload)
     eng = B.Engine(0)
     eng.set_problem(0, prob)
+    if args.electrons > 0:
+        iev = [P.MEAN_EXCITATION_EV[next(k for k in P.MATERIALS
+                                         if tuple(P.MATERIALS[k][:2]) == tuple(m))]
+               for m in prob.materials]
+        B.nmd_set_electrons(eng.ctx, 0, args.electrons, iev)
+        what += "; Compton electrons above %g MeV walked (CSDA, straight ahead)" % args.electrons
     opts = B.nmd_run_opts_default()
     opts.photons_per_decay = prob.photons_per_decay
     stream = torch.cuda.current_stream()
@@ -273,8 +283,10 @@ def bench_mc(args):
         "data": "synthetic",
         "config": {"workload": what, "decays_per_step": nd, "decays_per_job": total,
                    "photons_per_decay": prob.photons_per_decay,
+                   "electron_cutoff_mev": args.electrons or None,
                    "tally": "f64", "transport": "f32"},
         "roofline": transport_roofline(per_decay, nd, kern_ms,
+                                       None if args.electrons else
                                        TRAFFIC_BYTES_PER_DECAY.get(args.workload),
                                        atomic_ceiling),
     }

@@ -138,6 +138,27 @@ nmd_status nmd_set_phantom(nmd_ctx *ctx, int32_t phantom_id, int32_t nx, int32_t
 nmd_status nmd_set_activity(nmd_ctx *ctx, int32_t phantom_id, const float *activity_bq_ml,
                             double total_activity_bq);
 
+/* Electron transport above a cutoff (Section 2.1 follows electrons down to
+ * a 200 keV cutoff).  With cutoff_mev > 0, every Compton electron whose
+ * kinetic energy T exceeds it is walked from the interaction point in a
+ * straight line along its recoil momentum (E d_in - E' d_out) through the
+ * voxel grid, slowing down continuously: in each voxel it loses what the
+ * voxel's mass path rho * s takes off its range above the cutoff, the range
+ * being the integral of 1/S over [cutoff, T] with S the Bethe collision
+ * stopping power (ICRU Report 37 form, Moller term, no density effect, no
+ * radiative loss) of the voxel's material; where the range runs out it
+ * leaves all it still has, and energy it carries out of the grid is booked
+ * as escaped.  Electrons at or below the cutoff, and photoelectrons, are
+ * deposited on the spot.  cutoff_mev: 0 (electrons deposited on the spot,
+ * the default) or [0.001, 0.3] MeV; mean_excitation_ev: host
+ * double[n_materials], the mean excitation energy I of each material of
+ * nmd_set_phantom, in (1, 10^4) eV.  The library tabulates each material's
+ * range and inverse range on 256 nodes.  Resets the phantom's tallies;
+ * re-registering the phantom drops the model; checkpoints do not record
+ * it.  Synchronises the stream. */
+nmd_status nmd_set_electrons(nmd_ctx *ctx, int32_t phantom_id, double cutoff_mev,
+                             const double *mean_excitation_ev);
+
 /* ---- transport ----------------------------------------------------------- */
 
 /* Simulate n_decays histories of phantom `phantom_id`, or of every phantom

@@ -81,7 +81,8 @@ EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_get_ledger", "nmd_get_run_stats", "nmd_get_tallies", "nmd_set_tallies",
            "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
            "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
-           "nmd_graph_launch", "nmd_graph_destroy", "nmd_save", "nmd_load") + NN_EXPORTS + INGEST_EXPORTS + \
+           "nmd_graph_launch", "nmd_graph_destroy", "nmd_save", "nmd_load",
+           "nmd_set_electrons") + NN_EXPORTS + INGEST_EXPORTS + \
     PROBE_EXPORTS
 
 _lib = None
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(vp)],
         "nmd_graph_launch": [vp],
         "nmd_save": [vp, i32, ctypes.c_char_p],
+        "nmd_set_electrons": [vp, i32, d, vp],
         "nmd_load": [vp, i32, ctypes.c_char_p],
         "nmd_graph_destroy": [vp],
         "nmd_conv3d_fwd": [vp, i32, i32, i32, i32, ctypes.POINTER(nmd_nn_src), vp, vp, i32, i32,
@@ -267,6 +269,17 @@ def nmd_read_organ_dose(ctx, phantom_id, n_organs, sigma=True):
     _check(ctx, load_library().nmd_read_organ_dose(ctx, int(phantom_id), int(n_organs), p(r),
                                                    p(e), p(s)))
     return r, e, s
+
+
+def nmd_set_electrons(ctx, phantom_id, cutoff_mev, mean_excitation_ev=None):
+    """cutoff_mev 0 turns electron transport off; else one mean excitation
+    energy (eV) per material of the phantom."""
+    arr = None
+    if mean_excitation_ev is not None:
+        arr = np.ascontiguousarray(mean_excitation_ev, dtype=np.float64)
+    _check(ctx, load_library().nmd_set_electrons(
+        ctx, int(phantom_id), float(cutoff_mev),
+        None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)))
 
 
 def nmd_save(ctx, phantom_id, path):

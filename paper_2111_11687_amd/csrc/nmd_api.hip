@@ -72,6 +72,11 @@ struct Phantom {
   double a_ts = 0.0;
   uint64_t n_done = 0;
   uint64_t organ_from = 0;  // histories run before the organ sums O, O2 started
+  std::vector<int> pal_mat;  // palette index -> index into this phantom's materials (-1: unused)
+  int n_mat = 0;
+  std::vector<double> mat_zoa;  // Z/A of each material
+  DevBuf e_tab, e_inv_dr, e_slot;  // electron range tables (nmd_set_electrons)
+  float e_cut = 0.0f, e_inv_dt = 0.0f;
   uint64_t geom_hash = 0;   // FNV-1a of the voxel records, for checkpoints
   uint64_t act_hash = 0;    // FNV-1a of the alias table, for checkpoints
   double vkg() const { return dx * dy * dz * 1.0e-3; }  // kg per (g/cm^3)
@@ -164,6 +169,50 @@ void pal_coeffs(double z, double zoa, double rho, double &cc, double &cpe, doubl
   cr = rho * kNA * zoa * a_r * z * kERef * kERef;
 }
 
+// ---- electron ranges (host) ------------------------------------------------
+// Collision stopping power of electrons (Bethe, ICRU Report 37 form with the
+// Moller term, no density effect), MeV cm^2/g, for kinetic energy t (MeV),
+// electron fraction zoa and mean excitation energy i_ev.
+double electron_stopping(double t, double zoa, double i_ev) {
+  const double k = 2.0 * M_PI * kRe * kRe * kMeC2 * kNA;  // MeV cm^2 / mol
+  const double tau = t / kMeC2;
+  const double g2 = (tau + 1.0) * (tau + 1.0);
+  const double beta2 = tau * (tau + 2.0) / g2;
+  const double fminus = 1.0 - beta2 + (tau * tau / 8.0 - (2.0 * tau + 1.0) * M_LN2) / g2;
+  const double i_rel = i_ev * 1e-6 / kMeC2;
+  return k * zoa / beta2 * (std::log(tau * tau * (tau + 2.0) / (2.0 * i_rel * i_rel)) + fminus);
+}
+
+constexpr double kETabTop = 0.345;  // MeV, above the largest Compton electron of 0.511 MeV
+
+// Range above the cutoff, R(T) = integral_cut^T dT' / S(T') (g/cm^2), on the
+// kETab nodes T_i = cut + i dt, and its inverse T(R) on R_j = j dr, for one
+// material; the integral by 3-point Gauss-Legendre on 16 sub-intervals of
+// every node interval.
+void electron_tables(double cut, double zoa, double i_ev, float *r_tab, float *t_tab,
+                     float *inv_dr) {
+  const int sub = 16, nf = (kETab - 1) * sub;
+  const double dt = (kETabTop - cut) / (kETab - 1), h = dt / sub;
+  const double xg[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)}, wg[3] = {5.0 / 9, 8.0 / 9, 5.0 / 9};
+  std::vector<double> rf(nf + 1, 0.0);
+  for (int k = 0; k < nf; ++k) {
+    const double c = cut + (k + 0.5) * h;
+    double acc = 0.0;
+    for (int q = 0; q < 3; ++q) acc += wg[q] / electron_stopping(c + 0.5 * h * xg[q], zoa, i_ev);
+    rf[k + 1] = rf[k] + 0.5 * h * acc;
+  }
+  for (int i = 0; i < kETab; ++i) r_tab[i] = (float)rf[i * sub];
+  const double rmax = rf[nf], dr = rmax / (kETab - 1);
+  int k = 0;
+  for (int j = 0; j < kETab; ++j) {
+    const double r = std::min(j * dr, rmax);
+    while (k < nf - 1 && rf[k + 1] < r) ++k;
+    const double f = (r - rf[k]) / (rf[k + 1] - rf[k]);
+    t_tab[j] = (float)(cut + (k + std::min(std::max(f, 0.0), 1.0)) * h);
+  }
+  *inv_dr = (float)(1.0 / dr);
+}
+
 float round_up_f32(double x) {
   float f = (float)x;
   if ((double)f < x) f = std::nextafter(f, INFINITY);
@@ -220,6 +269,11 @@ PhantomDesc make_desc(int32_t id, const Phantom &p) {
   d.inv_dz = (float)(1.0 / p.dz);
   d.n_alias = p.n_alias;
   d.pid = (uint32_t)id;
+  d.e_tab = p.e_tab.as<float>();
+  d.e_inv_dr = p.e_inv_dr.as<float>();
+  d.e_slot = p.e_slot.as<uint8_t>();
+  d.e_cut = p.e_cut;
+  d.e_inv_dt = p.e_inv_dt;
   return d;
 }
 
@@ -268,6 +322,7 @@ struct RunPlan {
   RunIds ids;
   int grid = 0;
   bool debug = false;
+  bool electrons = false;   // some phantom of the run walks its Compton electrons
   bool auto_chunk = false;  // caller asked for the tuned chunk
   bool tuned = false;       // a tuned chunk was known
   uint32_t abort_after = 0;
@@ -362,7 +417,9 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
   int n_slots = 1;
   for (int32_t i : ids) n_slots = std::max(n_slots, c->ph[i].n_org + 1);
   pl.debug = o.history_records != nullptr;
-  const int per_cu = transport_occupancy_blocks_per_cu(pl.debug, n_slots);
+  pl.electrons = false;
+  for (int32_t i : ids) pl.electrons = pl.electrons || c->ph[i].e_cut > 0.0f;
+  const int per_cu = transport_occupancy_blocks_per_cu(pl.debug, pl.electrons, n_slots);
   uint32_t grid = o.grid_blocks ? o.grid_blocks : (uint32_t)(c->cu_count * per_cu);
   grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, 8192));
   pl.grid = (int)grid;
@@ -435,7 +492,7 @@ nmd_status enqueue_run(nmd_ctx *c, RunPlan &pl, unsigned long long *queue, uint3
   pl.rp.dep_e = dep_e;
   pl.rp.dep_r = dep_r;
   HIP_TRY(c, launch_zero_bytes(queue, 2 * sizeof(unsigned long long), st));
-  HIP_TRY(c, launch_transport(pl.rp, pl.grid, pl.debug, st));
+  HIP_TRY(c, launch_transport(pl.rp, pl.grid, pl.debug, pl.electrons, st));
   if (!advance) return NMD_OK;
   uint64_t n = pl.rp.n_ph ? pl.rp.slot[0].n_hist : 0;
   HIP_TRY(c, launch_advance(pl.rp.desc, pl.ids, n, st));
@@ -681,6 +738,7 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
   std::vector<int> mat_pal_base(n_mat);
   std::vector<uint16_t> rec(nvox);
   std::vector<uint8_t> used(kMaxPalette, 0);
+  std::vector<int> pal_mat(kMaxPalette, -1);
   uint64_t last_key = ~0ull;
   int last_q = 0;
   for (uint64_t v = 0; v < nvox; ++v) {
@@ -725,6 +783,7 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
     }
     rec[v] = (uint16_t)(last_q | (label ? (uint32_t)h_lab[v] << 8 : 0u));
     used[last_q] = 1;
+    pal_mat[last_q] = m;
   }
   std::vector<int64_t> count(n_organs + 1, 0);
   if (label) {
@@ -747,6 +806,9 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
   p.nvox = nvox;
   p.organ_count = count;
   p.used = used;
+  p.pal_mat = pal_mat;
+  p.n_mat = n_mat;
+  for (int m = 0; m < n_mat; ++m) p.mat_zoa.push_back(mats[m].z_over_a);
   {
     const int32_t hd[3] = {nx, ny, nz};
     uint64_t h = fnv1a(hd, sizeof hd);
@@ -866,6 +928,54 @@ nmd_status nmd_set_activity(nmd_ctx *c, int32_t id, const float *act, double tot
   p->has_activity = true;
   p->a_ts = total_bq > 0.0 ? total_bq : sum * (p->dx * p->dy * p->dz);
   if ((s = zero_tallies(c, *p))) return s;
+  return upload_desc(c, id, *p);
+}
+
+nmd_status nmd_set_electrons(nmd_ctx *c, int32_t id, double cutoff_mev,
+                             const double *mean_excitation_ev) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (cutoff_mev == 0.0) {
+    p->e_tab.release();
+    p->e_inv_dr.release();
+    p->e_slot.release();
+    p->e_cut = 0.0f;
+    p->e_inv_dt = 0.0f;
+  } else {
+    if (!(cutoff_mev >= 0.001 && cutoff_mev <= 0.3))
+      return fail(c, NMD_E_INVALID, "electron cutoff must be 0 or lie in [0.001, 0.3] MeV");
+    if (!mean_excitation_ev)
+      return fail(c, NMD_E_INVALID, "mean excitation energies are required");
+    for (int m = 0; m < p->n_mat; ++m)
+      if (!(mean_excitation_ev[m] > 1.0 && mean_excitation_ev[m] < 1.0e4))
+        return fail(c, NMD_E_INVALID, "mean excitation energy of material %d must lie in "
+                    "(1, 10^4) eV", m);
+    const float cut = (float)cutoff_mev;
+    std::vector<float> tab((size_t)kMaxMaterials * 2 * kETab, 0.0f), inv_dr(kMaxMaterials, 0.0f);
+    for (int m = 0; m < p->n_mat; ++m)
+      electron_tables((double)cut, p->mat_zoa[m], mean_excitation_ev[m], &tab[(size_t)m * 2 * kETab],
+                      &tab[(size_t)m * 2 * kETab + kETab], &inv_dr[m]);
+    std::vector<uint8_t> slot(kMaxPalette, 0);
+    for (int q = 0; q < kMaxPalette; ++q) slot[q] = (uint8_t)std::max(p->pal_mat[q], 0);
+    DevBuf dt, dr, ds;
+    if ((s = dev_alloc(c, dt, tab.size() * sizeof(float))) ||
+        (s = dev_alloc(c, dr, inv_dr.size() * sizeof(float))) ||
+        (s = dev_alloc(c, ds, slot.size())))
+      return s;
+    HIP_TRY(c, hipMemcpyAsync(dt.p, tab.data(), dt.n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dr.p, inv_dr.data(), dr.n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ds.p, slot.data(), ds.n, hipMemcpyHostToDevice, c->stream));
+    if ((s = sync(c))) return s;
+    p->e_tab = std::move(dt);
+    p->e_inv_dr = std::move(dr);
+    p->e_slot = std::move(ds);
+    p->e_cut = cut;
+    p->e_inv_dt = (float)((kETab - 1) / (kETabTop - (double)cut));
+  }
+  p->gen = c->next_gen++;
+  if (p->has_activity && (s = zero_tallies(c, *p))) return s;
   return upload_desc(c, id, *p);
 }
 

@@ -25,6 +25,8 @@ constexpr uint32_t kPhaseMinInt = 24, kPhaseMinEnd = 40;
 constexpr int kFlySteps = 2;              // Woodcock steps per flight pass and photon
 constexpr int kOrgCache = 3;              // organ score slots per history, in registers
 constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
+constexpr int kETab = 256;                // nodes of the electron range and inverse-range tables
+constexpr int kMaxMaterials = 8;
 
 // Workgroups of the transport kernel the compiler must fit on one CU (it
 // caps registers accordingly); a build-time tuning knob.
@@ -60,6 +62,15 @@ struct PhantomDesc {
   float dx, dy, dz, inv_dx, inv_dy, inv_dz;
   uint32_t n_alias;
   uint32_t pid;
+  // Compton electrons above e_cut (MeV; 0 = every electron deposited on the
+  // spot) walk straight ahead through the grid: per material slot s the
+  // CSDA range above the cutoff R_s(T) (g/cm^2) on the nodes
+  // T_i = e_cut + i / e_inv_dt, and its inverse T_s(R) on R_j = j / inv_dr_s
+  const float *e_tab;    // [kMaxMaterials][2][kETab]: R_s(T_i), then T_s(R_j)
+  const float *e_inv_dr; // [kMaxMaterials]
+  const uint8_t *e_slot; // [kMaxPalette]: palette index -> material slot
+  float e_cut;
+  float e_inv_dt;
 };
 
 // Per-run fields of one phantom of a launch.
@@ -108,8 +119,9 @@ struct RunParams {
   RunSlot slot[kMaxPhantoms];
 };
 
-hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_t s);
-int transport_occupancy_blocks_per_cu(bool debug, int n_slots);
+hipError_t launch_transport(const RunParams &p, int grid, bool debug, bool electrons,
+                            hipStream_t s);
+int transport_occupancy_blocks_per_cu(bool debug, bool electrons, int n_slots);
 size_t transport_dyn_lds_bytes(int n_slots);
 hipError_t launch_finalize(const uint16_t *rec, const float4 *palette, const double2 *tally,
                            uint64_t nvox, const unsigned long long *n_decays,

@@ -110,7 +110,7 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <bool kDebug>
+template <bool kDebug, bool kElectrons>
 __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_kernel(RunParams P) {
   __shared__ float4 s_pal[kMaxPalette];
   __shared__ double s_irho[kMaxPalette];  // 1 / density, for the organ scores
@@ -569,6 +569,103 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     ++cnt;
   };
 
+  // Walk a Compton electron of kinetic energy t0 (MeV, exact in FP64) from
+  // the photon's event point along (qx, qy, qz), its recoil momentum E d_in
+  // - E' d_out, in a straight line voxel by voxel (continuous slowing down;
+  // Section 2.1 follows electrons down to its electron cutoff).  In each
+  // voxel it loses what the voxel's mass path takes off its range above the
+  // cutoff; where that range runs out it leaves all it still has.  Each loss
+  // goes to the history's deposit list; returns the energy carried out of
+  // the grid.
+  auto electron_walk = [&](float qx, float qy, float qz, double t0) -> double {
+    CDesc *d = D;
+    const float qq = qx * qx + qy * qy + qz * qz;
+    if (!(qq > 0.0f)) {  // no recoil direction: the energy stays at the event
+      atomicAdd(&wa.stat[7], 1ull);
+      deposit(ev_v, ev_r, t0);
+      return 0.0;
+    }
+    const float qn = __builtin_amdgcn_rsqf(qq);
+    qx *= qn;
+    qy *= qn;
+    qz *= qn;
+    const float h[3] = {d->dx, d->dy, d->dz};
+    const float pos[3] = {px, py, pz};
+    const float qv[3] = {qx, qy, qz};
+    const int32_t n[3] = {d->nx, d->ny, d->nz};
+    // the event voxel, as the flight step found it
+    int iv[3] = {(int)(px * d->inv_dx), (int)(py * d->inv_dy), (int)(pz * d->inv_dz)};
+    float tn[3], td[3];
+    int sp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (qv[a] > 0.0f) {
+        sp[a] = 1;
+        tn[a] = ((float)(iv[a] + 1) * h[a] - pos[a]) / qv[a];
+        td[a] = h[a] / qv[a];
+      } else if (qv[a] < 0.0f) {
+        sp[a] = -1;
+        tn[a] = ((float)iv[a] * h[a] - pos[a]) / qv[a];
+        td[a] = -h[a] / qv[a];
+      } else {
+        sp[a] = 0;
+        tn[a] = __builtin_inff();
+        td[a] = __builtin_inff();
+      }
+      tn[a] = fmaxf(tn[a], 0.0f);
+    }
+    const float cut = d->e_cut, inv_dt = d->e_inv_dt;
+    double t = t0;
+    float tf = (float)t0;
+    float s_cur = 0.0f;
+    for (;;) {
+      const uint32_t v =
+          (uint32_t)iv[0] + (uint32_t)n[0] * ((uint32_t)iv[1] + (uint32_t)n[1] * (uint32_t)iv[2]);
+      const uint32_t r16 = G(d->rec)[v];
+      const uint32_t pq = r16 & 0xFFu;
+      const float rho = s_pal[pq].w;
+      const uint32_t slot = G(d->e_slot)[pq];
+      const float *tab = d->e_tab + slot * (2 * kETab);
+      int ax = 0;  // ties go to the lower axis
+      if (tn[1] < tn[ax]) ax = 1;
+      if (tn[2] < tn[ax]) ax = 2;
+      const float tnext = ax == 0 ? tn[0] : (ax == 1 ? tn[1] : tn[2]);
+      const float mass = rho * (tnext - s_cur);
+      // range above the cutoff in this voxel's material
+      const float u = (tf - cut) * inv_dt;
+      int i = (int)u;
+      i = i < 0 ? 0 : (i > kETab - 2 ? kETab - 2 : i);
+      const float r0 = G(tab)[i], r1 = G(tab)[i + 1];
+      const float range = r0 + (u - (float)i) * (r1 - r0);
+      const bool stop = mass >= range;
+      // energy after the voxel (the cutoff's share stays with the last one)
+      float t1 = 0.0f;
+      if (!stop) {
+        const float w = (range - mass) * G(d->e_inv_dr)[slot];
+        int j = (int)w;
+        j = j < 0 ? 0 : (j > kETab - 2 ? kETab - 2 : j);
+        const float e0 = G(tab)[kETab + j], e1 = G(tab)[kETab + j + 1];
+        t1 = fminf(fmaxf(e0 + (w - (float)j) * (e1 - e0), cut), tf);
+      }
+      atomicAdd(&wa.stat[7], 1ull);
+      deposit(v, r16, t - (double)t1);  // one call site: one inlined copy
+      if (stop) return 0.0;
+      t = (double)t1;
+      tf = t1;
+      s_cur = tnext;
+      int k = -1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a == ax) {
+          iv[a] += sp[a];
+          tn[a] += td[a];
+          k = iv[a] < 0 || iv[a] >= n[a] ? a : k;
+        }
+      }
+      if (k >= 0) return t;
+    }
+  };
+
   // Claim histories for the idle lanes from the wave's chunk, claiming new
   // chunks (or switching phantom once the wave has drained) as needed.
   auto refill = [&]() {
@@ -662,17 +759,37 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
             const float uphi = st.uniform();
             const float e1 = eps * E;
             dep = (double)E - (double)e1;  // exact in FP64
-            atomicAdd(&wa.ledger[1], dep);
-            rotate(ux, uy, uz, cost, uphi);
+            bool walked = false;
+            if constexpr (kElectrons) {
+              if (D->e_cut > 0.0f && dep > (double)D->e_cut) {
+                // the electron is tracked from the event point
+                const float dx0 = ux, dy0 = uy, dz0 = uz;
+                rotate(ux, uy, uz, cost, uphi);
+                const double out = electron_walk(E * dx0 - e1 * ux, E * dy0 - e1 * uy,
+                                                 E * dz0 - e1 * uz, dep);
+                atomicAdd(&wa.ledger[1], dep - out);
+                if (out > 0.0) {
+                  atomicAdd(&wa.ledger[4], out);
+                  if (kDebug) h_esc += out;
+                }
+                walked = true;
+              }
+            }
+            if (!walked) {
+              atomicAdd(&wa.ledger[1], dep);
+              rotate(ux, uy, uz, cost, uphi);
+            }
             E = e1;
             if (E < P.cutoff) {
-              // the cutoff energy stays in the same voxel: T + E' = E
+              // the cutoff energy stays in the same voxel: T + E' = E (or
+              // E' alone when the electron has walked off with T)
               atomicAdd(&wa.ledger[3], (double)E);
-              atomicAdd(&wa.stat[7], 1ull);
-              dep += (double)E;
+              if (!walked) atomicAdd(&wa.stat[7], 1ull);
+              dep = walked ? (double)E : dep + (double)E;
               pdone = true;
             } else {
               ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+              if (walked) dep = -1.0;  // nothing left at the event point
             }
           } else if (ev_t == 2) {
             if (kDebug) ++h_pe_esc;
@@ -826,20 +943,30 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   flush_wave();
 }
 
-int transport_occupancy_blocks_per_cu(bool debug, int n_slots) {
+int transport_occupancy_blocks_per_cu(bool debug, bool electrons, int n_slots) {
   int nb = 0;
   const size_t dyn = transport_dyn_lds_bytes(n_slots);
-  hipError_t e = debug ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true>, kBlock, dyn)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false>, kBlock, dyn);
+  hipError_t e;
+  if (debug)
+    e = electrons ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true, true>, kBlock, dyn)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true, false>, kBlock, dyn);
+  else
+    e = electrons ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false, true>, kBlock, dyn)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false, false>, kBlock, dyn);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-hipError_t launch_transport(const RunParams &p, int grid, bool debug, hipStream_t s) {
+hipError_t launch_transport(const RunParams &p, int grid, bool debug, bool electrons,
+                            hipStream_t s) {
   const size_t dyn = transport_dyn_lds_bytes(p.n_slots);
-  if (debug)
-    hipLaunchKernelGGL(transport_kernel<true>, dim3(grid), dim3(kBlock), dyn, s, p);
+  if (debug && electrons)
+    hipLaunchKernelGGL((transport_kernel<true, true>), dim3(grid), dim3(kBlock), dyn, s, p);
+  else if (debug)
+    hipLaunchKernelGGL((transport_kernel<true, false>), dim3(grid), dim3(kBlock), dyn, s, p);
+  else if (electrons)
+    hipLaunchKernelGGL((transport_kernel<false, true>), dim3(grid), dim3(kBlock), dyn, s, p);
   else
-    hipLaunchKernelGGL(transport_kernel<false>, dim3(grid), dim3(kBlock), dyn, s, p);
+    hipLaunchKernelGGL((transport_kernel<false, false>), dim3(grid), dim3(kBlock), dyn, s, p);
   return hipGetLastError();
 }
 
