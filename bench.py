@@ -46,7 +46,7 @@ HBM_PEAK = 8.0e12  # bytes/s
 # WRITE_SIZE of rocprofv3 --pmc runs, scaled against a profiled 256 MiB copy
 # (profiles/transport_patient256x256x320_counters.md).  Only workloads whose
 # counters were taken with the current kernel have an entry.
-TRAFFIC_BYTES_PER_DECAY = {"patient": 1769.0}
+TRAFFIC_BYTES_PER_DECAY = {"patient": 1950.0}
 
 
 def valu_ops(stats):
@@ -65,29 +65,51 @@ def hbm_bytes(stats):
     return 16.0 * stats["histories"] + 2.0 * stats["steps"] + 32.0 * stats["merged"]
 
 
-def measure_atomic_ceiling(ctx):
-    """FP64 atomic adds/s at scattered addresses of a 256 MiB table (the
-    patient's tally is 320 MiB), measured on this device before the timed
-    region."""
+def measure_ceilings(ctx, record_bytes):
+    """Ceilings of the transport's two memory-side paths, measured on this
+    device before the timed region: FP64 atomic adds/s at scattered addresses
+    of a 256 MiB table (the patient's tally is 320 MiB), and 2-byte loads/s at
+    scattered addresses of an array of the voxel records' size rounded up to
+    a power of two."""
     from paper_2111_11687_amd import binding as B
-    return B.nmd_probe_ceiling(ctx, "atomic_f64", 256 << 20, 5)[0]
+    gb = 1 << 20
+    while gb < record_bytes and gb < (8 << 30):
+        gb <<= 1
+    return {"atomic": B.nmd_probe_ceiling(ctx, "atomic_f64", 256 << 20, 5)[0],
+            "gather": B.nmd_probe_ceiling(ctx, "gather_u16", gb, 5)[0],
+            "gather_bytes": gb}
 
 
-def transport_roofline(per_decay, nd, kern_ms, traffic_per_decay, atomic_ceiling):
-    """Roofline of one transport launch of nd decays lasting kern_ms.  Its
-    binding ceiling is the FP64 atomic rate: two atomics (S and S2) per
-    merged deposit; the VALU and HBM terms are reported beside it."""
+def transport_roofline(per_decay, nd, kern_ms, traffic_per_decay, ceil):
+    """Roofline of one transport launch of nd decays lasting kern_ms against
+    measured ceilings: the FP64 atomics (two per merged deposit, S and S2)
+    and the voxel-record gathers of the flight steps (the run's own count).
+    The bound is the one nearer its ceiling; the other, and the VALU and HBM
+    terms, are reported beside it."""
     ops, byt = valu_ops(per_decay), hbm_bytes(per_decay)
-    atom = 2.0 * per_decay["merged"]
     sec = kern_ms * 1e-3
-    achieved = atom * nd / sec
-    return {"bound": "atomic", "achieved": achieved / 1e9, "peak": atomic_ceiling / 1e9,
-            "unit": "G FP64 atomics/s", "frac": achieved / atomic_ceiling,
-            "peak_source": "measured on this device: scattered FP64 atomic adds, 256 MiB table",
+    atom = 2.0 * per_decay["merged"]
+    gath = per_decay["gathers"]
+    terms = {
+        "atomic": {"per_decay": atom, "achieved": atom * nd / sec / 1e9,
+                   "peak": ceil["atomic"] / 1e9, "unit": "G FP64 atomics/s",
+                   "frac": atom * nd / sec / ceil["atomic"],
+                   "peak_source": "measured on this device: scattered FP64 atomic adds, "
+                                  "256 MiB table"},
+        "gather": {"per_decay": gath, "achieved": gath * nd / sec / 1e9,
+                   "peak": ceil["gather"] / 1e9, "unit": "G voxel-record gathers/s",
+                   "frac": gath * nd / sec / ceil["gather"],
+                   "peak_source": "measured on this device: scattered 2-byte loads, "
+                                  "%d MiB array" % (ceil["gather_bytes"] >> 20)}}
+    bound = max(terms, key=lambda k: terms[k]["frac"])
+    other = "atomic" if bound == "gather" else "gather"
+    b = terms[bound]
+    return {"bound": bound, "achieved": b["achieved"], "peak": b["peak"], "unit": b["unit"],
+            "frac": b["frac"], "peak_source": b["peak_source"],
             "traffic": None if traffic_per_decay is None else traffic_per_decay * nd,
             "traffic_unit": "bytes beyond L2 per launch (profiled)",
             "kernel": "transport_kernel", "kernel_ms": kern_ms,
-            "atomics_per_decay": atom,
+            "per_decay": b["per_decay"], other: terms[other],
             "valu": {"ops_per_decay": ops, "achieved_tops": ops * nd / sec / 1e12,
                      "peak_tops": VALU_PEAK_OPS / 1e12,
                      "frac": ops * nd / sec / VALU_PEAK_OPS},
@@ -245,7 +267,7 @@ def bench_mc(args):
     for _ in range(args.warmup):
         step()
     B.nmd_reset_tallies(eng.ctx, 0)
-    atomic_ceiling = measure_atomic_ceiling(eng.ctx)
+    ceilings = measure_ceilings(eng.ctx, 2 * prob.nvox)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
@@ -288,7 +310,7 @@ def bench_mc(args):
         "roofline": transport_roofline(per_decay, nd, kern_ms,
                                        None if args.electrons else
                                        TRAFFIC_BYTES_PER_DECAY.get(args.workload),
-                                       atomic_ceiling),
+                                       ceilings),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
@@ -392,6 +414,21 @@ def bench_batch(args):
     total = args.steps * nd * len(probs)
     launch_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     organs = B.nmd_read_organ_dose(eng.ctx, 0, probs[0].n_organs)
+    # the transport kernel alone, for the roofline: one eager launch of the
+    # same work after the timed region, with its counters
+    ceilings = measure_ceilings(eng.ctx, 2 * sum(p.nvox for p in probs))
+    B.nmd_reset_tallies(eng.ctx, -1)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    ev[0].record(stream)
+    B.nmd_run_histories(eng.ctx, -1, nd, 4001, None)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    kern_ms = ev[0].elapsed_time(ev[1])
+    sums = {}
+    for i in range(len(probs)):
+        for k, v in eng.stats(i).items():
+            sums[k] = sums.get(k, 0) + v
+    per_decay = {k: v / (nd * len(probs)) for k, v in sums.items()}
     print(json.dumps({"tune_run_s": t_tune, "steps_ms": [a.elapsed_time(b) for a, b in evs],
                       "voxels": sum(p.nvox for p in probs),
                       "phantom0_organ_rate": organs[0][:5].tolist()}), file=sys.stderr)
@@ -404,7 +441,12 @@ def bench_batch(args):
                                "2-4 mm, 10^7 decays each per step, hipGraph replay",
                    "voxels": sum(p.nvox for p in probs), "chunk": chunk, "grid_blocks": grid,
                    "graph_launch_ms": launch_ms},
+        "roofline": transport_roofline(per_decay, nd * len(probs), kern_ms, None,
+                                       ceilings),
     }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(probs[0], args.cpu_seconds)
+        out["cpu_baseline"]["sample"] += " (the batch's first phantom)"
     eng.close()
     print(json.dumps(out), flush=True)
 

@@ -90,13 +90,16 @@ typedef struct {
  * deposit voxels (64) was full: each is scored on its own, so every mean
  * (Eq. 1, Eq. 2) stays exact but the history's square for that voxel and
  * organ is split, which biases the uncertainties low; a nonzero count marks
- * them as approximate. */
+ * them as approximate.  NMD_STAT_GATHERS counts the voxel records the flight
+ * steps read: at least one per step inside the grid, plus the records read
+ * ahead for a second step that a real collision or an escape then made
+ * unnecessary. */
 enum { NMD_LEDGER_EMITTED = 0, NMD_LEDGER_DEP_COMPTON, NMD_LEDGER_DEP_PE, NMD_LEDGER_DEP_CUTOFF,
        NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_N };
 enum { NMD_STAT_HISTORIES = 0, NMD_STAT_PHOTONS, NMD_STAT_STEPS, NMD_STAT_NULLS,
        NMD_STAT_COMPTON, NMD_STAT_PE, NMD_STAT_RAYLEIGH, NMD_STAT_DEPOSITS, NMD_STAT_MERGED,
        NMD_STAT_MAX_MERGED, NMD_STAT_ESCAPES, NMD_STAT_OVERFLOWS, NMD_STAT_CLAIMS,
-       NMD_STAT_RNG_BLOCKS, NMD_STAT_LIST_MERGES, NMD_STAT_N };
+       NMD_STAT_RNG_BLOCKS, NMD_STAT_LIST_MERGES, NMD_STAT_GATHERS, NMD_STAT_N };
 
 /* ---- context ------------------------------------------------------------ */
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnmdose.so")
 LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded")
 STATS_FIELDS = ("histories", "photons", "steps", "nulls", "compton", "photoelectric",
                 "rayleigh", "deposits", "merged", "max_merged", "escapes", "overflows",
-                "claims", "rng_blocks", "list_merges")
+                "claims", "rng_blocks", "list_merges", "gathers")
 HREC_FIELDS = ("edep", "escaped", "n_compton", "n_pe", "n_rayleigh", "n_steps",
                "sum_voxel", "n_merged", "n_uniforms", "discarded")
 STATUS = {0: "NMD_OK", -1: "NMD_E_INVALID", -2: "NMD_E_SHAPE", -3: "NMD_E_STATE",

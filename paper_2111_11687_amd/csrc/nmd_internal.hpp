@@ -18,7 +18,7 @@ constexpr int kBlock = 256;             // transport workgroup size (4 waves)
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kMaxOrganSlots = 256;     // labels 0..255
 constexpr int kRecN = 10;               // per-history debug record width
-constexpr int kStatN = 15;
+constexpr int kStatN = 16;
 // lanes that wait before their phase runs (unless they outnumber the
 // flights): interactions, and history ends (the costlier pass)
 constexpr uint32_t kPhaseMinInt = 24, kPhaseMinEnd = 40;

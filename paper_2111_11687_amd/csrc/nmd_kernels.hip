@@ -866,21 +866,53 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       // pass, the next one only after a null collision, so the pass's fixed
       // costs (phase choice, generator refill) are shared by more steps
       uint32_t ns = 0u, nn = 0u, ne = 0u;  // this lane's steps, null collisions, escapes
+      uint32_t ng = 0u;                    // and the voxel records it read
       if (state == kFlight) {
         st.reserve4();  // two steps' draws, refilled for all flying lanes at once
+        // A step's length does not depend on the voxel it ends in, so the
+        // end points of all the pass's steps are known before any voxel
+        // record is read: the records are gathered together, and a step's
+        // outcome is used only after null collisions on the steps before
+        // it.  Arithmetic and draws are those of taking the steps one by one.
+        const uint32_t w_len[2] = {st.b0, st.b2};  // each step's length word
+        float qx[kFlySteps], qy[kFlySteps], qz[kFlySteps];
+        bool qin[kFlySteps];
+        uint32_t qv[kFlySteps], qr[kFlySteps];
+        {
+          float cx = px, cy = py, cz = pz;
+#pragma unroll
+          for (int k = 0; k < kFlySteps; ++k) {
+            const float s = -fast_log2(Stream<kDebug>::to_uniform(w_len[k])) * ep.inv_mu_ln2;
+            cx += s * ux;
+            cy += s * uy;
+            cz += s * uz;
+            qx[k] = cx;
+            qy[k] = cy;
+            qz[k] = cz;
+            const float fx = cx * D->inv_dx, fy = cy * D->inv_dy, fz = cz * D->inv_dz;
+            // written so that a NaN coordinate counts as outside
+            qin[k] = fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
+                     fz < D->fnz;
+            qv[k] = qin[k] ? (uint32_t)fx + (uint32_t)D->nx *
+                                                ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz)
+                           : 0u;
+          }
+#pragma unroll
+          for (int k = 0; k < kFlySteps; ++k) {
+            qr[k] = qin[k] ? (uint32_t)G(D->rec)[qv[k]] : 0u;
+            ng += qin[k] ? 1u : 0u;
+          }
+        }
 #pragma unroll
         for (int k = 0; k < kFlySteps; ++k) {
           if (state != kFlight) break;
           if (kDebug) ++h_steps;
           ++ns;
-          const float s = -fast_log2(st.take_uniform()) * ep.inv_mu_ln2;
-          px += s * ux;
-          py += s * uy;
-          pz += s * uz;
-          const float fx = px * D->inv_dx, fy = py * D->inv_dy, fz = pz * D->inv_dz;
-          // written so that a NaN coordinate counts as outside
-          if (!(fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
-                fz < D->fnz)) {
+          (void)st.take();  // the step's length word, used above
+          px = qx[k];
+          py = qy[k];
+          pz = qz[k];
+          if (!qin[k]) {
             atomicAdd(&wa.ledger[4], (double)E);
             if (kDebug) h_pe_esc += 0x10000u;
             ++ne;
@@ -892,9 +924,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
             if (kDebug) h_disc += E;
             state = kPhotonEnd;
           } else {
-            const uint32_t v =
-                (uint32_t)fx + (uint32_t)D->nx * ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz);
-            const uint32_t r16 = G(D->rec)[v];
+            const uint32_t v = qv[k];
+            const uint32_t r16 = qr[k];
             const float4 pal = s_pal[r16 & 0xFFu];
             const float mc = pal.x * ep.sig;
             const float mpe = pal.y * ep.gpe;
@@ -920,8 +951,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         start_photon();
         state = kFlight;
       }
+      // per-lane counts are at most 2: count them by their binary digits
+      const uint32_t c_g = __popcll(__ballot(ng & 1u)) + 2u * __popcll(__ballot(ng & 2u));
+      if (lane == 0) atomicAdd(&wa.stat[15], (unsigned long long)c_g);
       if (!kDebug) {
-        // per-lane counts are at most 2: count them by their binary digits
         const uint32_t c_s = __popcll(__ballot(ns & 1u)) + 2u * __popcll(__ballot(ns & 2u));
         const uint32_t c_n = __popcll(__ballot(nn & 1u)) + 2u * __popcll(__ballot(nn & 2u));
         const uint32_t c_e = __popcll(__ballot(ne != 0u));
