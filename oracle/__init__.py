@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nmd_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-TRACK_EXACT, TRACK_WOODCOCK = 0, 1
+TRACK_EXACT, TRACK_WOODCOCK, TRACK_REGIONS = 0, 1, 2
 KN_KAHN, KN_BUTCHER = 0, 1
 RNG_PHILOX, RNG_XOSHIRO = 0, 1
 SRC_ACTIVITY, SRC_PENCIL = 0, 1

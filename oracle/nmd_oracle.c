@@ -20,13 +20,19 @@
  * log-log interpolation, secondary electrons deposited on the spot, vacuum
  * outside the grid.
  *
- * Two tracking modes:
+ * Three tracking modes:
  *   ORC_TRACK_EXACT    -- voxel-by-voxel ray traversal (Amanatides and Woo
  *                         1987), one optical depth per flight.  Independent
  *                         of the GPU's tracking; used for statistical parity.
  *   ORC_TRACK_WOODCOCK -- delta tracking against a majorant, consuming
  *                         uniforms in the documented per-history order so a
  *                         history can be replayed draw for draw.
+ *   ORC_TRACK_REGIONS  -- the same delta tracking with a majorant by region:
+ *                         the phantom's inside the bounding box of its dense
+ *                         voxels, a smaller one in the thin voxels around it.
+ *                         Not in the paper: a variant of its Woodcock step
+ *                         that samples the same model with fewer null
+ *                         collisions.
  * Two Klein-Nishina samplers: Kahn's rejection (1954) and the
  * Butcher-Messel composition-rejection.  Two random-number families, both
  * written here from their published definitions: Philox4x32-10 (Salmon et
@@ -68,7 +74,7 @@
 #define ORC_STATS_N 12
 #define ORC_HREC_N 10
 
-enum { ORC_TRACK_EXACT = 0, ORC_TRACK_WOODCOCK = 1 };
+enum { ORC_TRACK_EXACT = 0, ORC_TRACK_WOODCOCK = 1, ORC_TRACK_REGIONS = 2 };
 enum { ORC_KN_KAHN = 0, ORC_KN_BUTCHER = 1 };
 enum { ORC_SRC_ACTIVITY = 0, ORC_SRC_PENCIL = 1 };
 enum { ORC_EV_NULL = 0, ORC_EV_COMPTON = 1, ORC_EV_PE = 2, ORC_EV_RAYLEIGH = 3 };
@@ -420,7 +426,17 @@ typedef struct {
 typedef struct {
   double ln_mu_rho[8][3][ORC_NGRID];  /* ln of mass attenuation per process */
   double ln_major[ORC_NGRID];         /* ln of majorant (cm^-1)             */
+  /* Woodcock majorant by region: inside the box [box_lo, box_hi) (cm), the
+   * bounding box of every voxel at least ORC_INNER_RHO dense, the phantom's;
+   * elsewhere in the grid (thinner voxels only) out_ratio times it, the
+   * smallest multiple that bounds those voxels at every energy node.
+   * has_out is 0 when the box is the whole grid. */
+  double out_ratio;
+  double box_lo[3], box_hi[3];
+  int has_out;
 } orc_tables;
+
+#define ORC_INNER_RHO 0.01f /* g/cm^3, compared in single precision as stored */
 
 static void build_tables(const orc_phantom *ph, orc_tables *t)
 {
@@ -447,6 +463,55 @@ static void build_tables(const orc_phantom *ph, orc_tables *t)
     }
     t->ln_major[i] = log(mx);
   }
+  /* the box of the dense voxels, and the largest density per material
+   * outside it */
+  int64_t lo[3] = { ph->nx, ph->ny, ph->nz }, hi[3] = { 0, 0, 0 };
+  const int32_t n[3] = { ph->nx, ph->ny, ph->nz };
+  for (int64_t v = 0; v < nvox; ++v) {
+    if (!((float)ph->density[v] >= ORC_INNER_RHO)) continue;
+    const int64_t c[3] = { v % n[0], (v / n[0]) % n[1], v / ((int64_t)n[0] * n[1]) };
+    for (int a = 0; a < 3; ++a) {
+      if (c[a] < lo[a]) lo[a] = c[a];
+      if (c[a] + 1 > hi[a]) hi[a] = c[a] + 1;
+    }
+  }
+  if (hi[0] == 0)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = 0;
+      hi[a] = n[a];
+    }
+  const double h[3] = { ph->dx, ph->dy, ph->dz };
+  for (int a = 0; a < 3; ++a) {
+    t->box_lo[a] = (double)lo[a] * h[a];
+    t->box_hi[a] = (double)hi[a] * h[a];
+  }
+  double rho_out[8];
+  for (int m = 0; m < 8; ++m) rho_out[m] = 0.0;
+  t->has_out = 0;
+  for (int64_t v = 0; v < nvox; ++v) {
+    const int64_t c[3] = { v % n[0], (v / n[0]) % n[1], v / ((int64_t)n[0] * n[1]) };
+    int inside = 1;
+    for (int a = 0; a < 3; ++a) inside = inside && c[a] >= lo[a] && c[a] < hi[a];
+    if (inside) continue;
+    t->has_out = 1;
+    if (ph->density[v] > rho_out[ph->material[v]]) rho_out[ph->material[v]] = ph->density[v];
+  }
+  /* the ratio, widened by 2^-16 as the device widens its single-precision
+   * product */
+  t->out_ratio = 0.0;
+  for (int i = 0; t->has_out && i < ORC_NGRID; ++i) {
+    double mx = 0.0;
+    for (int m = 0; m < ph->n_mat; ++m) {
+      if (rho_out[m] <= 0.0) continue;
+      double s = 0.0;
+      for (int p = 0; p < 3; ++p) s += exp(t->ln_mu_rho[m][p][i]);
+      s *= rho_out[m];
+      if (s > mx) mx = s;
+    }
+    const double r = mx / exp(t->ln_major[i]);
+    if (r > t->out_ratio) t->out_ratio = r;
+  }
+  t->out_ratio *= 1.0 + 1.0 / 65536.0;
 }
 
 /* Mass attenuation of all materials and processes at energy e. */
@@ -465,6 +530,55 @@ static double eval_major(const orc_tables *t, double e)
   double f;
   grid_locate(e, &i, &f);
   return ORC_KAPPA * loglog(t->ln_major, i, f);
+}
+
+
+static int in_box(const orc_tables *t, const double r[3])
+{
+  for (int a = 0; a < 3; ++a)
+    if (!(r[a] >= t->box_lo[a] && r[a] < t->box_hi[a])) return 0;
+  return 1;
+}
+
+/* Path length of a Woodcock step whose optical depth against the current
+ * region's majorant is s * maj[*out]: the depth is spent region by region
+ * along the ray from r (inside the box: the phantom's majorant; outside it:
+ * the outer one).  The box is convex, so the ray crosses it along one
+ * interval [tn, tf] of its parameter, found once from r: a ray inside
+ * leaves at tf for good; a ray outside enters at tn (if at all) and leaves
+ * at tf.  *out ends as the region of the step's end point.  Without an
+ * outer region a ray leaving the box leaves the grid: the length is
+ * infinite. */
+static double region_walk(const orc_tables *t, const double r[3], const double d[3], double s,
+                          const double maj[2], int *out)
+{
+  double tau = s * maj[*out];
+  double tn = -INFINITY, tf = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] != 0.0) {
+      const double t1 = (t->box_lo[a] - r[a]) / d[a], t2 = (t->box_hi[a] - r[a]) / d[a];
+      const double a1 = t1 < t2 ? t1 : t2, a2 = t1 < t2 ? t2 : t1;
+      if (a1 > tn) tn = a1;
+      if (a2 < tf) tf = a2;
+    } else if (!(r[a] >= t->box_lo[a] && r[a] < t->box_hi[a])) {
+      tf = -INFINITY;
+    }
+  }
+  double t0 = 0.0; /* where the inside stretch starts */
+  if (*out) {
+    /* a ray that misses the box, or only touches it, stays outside */
+    if (!(tn < tf) || !(tf > 0.0) || tau <= maj[1] * (tn > 0.0 ? tn : 0.0))
+      return tau / maj[1];
+    t0 = tn > 0.0 ? tn : 0.0;
+    tau -= maj[1] * t0;
+    *out = 0;
+  }
+  const double tx = tf > t0 ? tf : t0; /* where the ray leaves the box */
+  if (tau <= maj[0] * (tx - t0)) return t0 + tau / maj[0];
+  tau -= maj[0] * (tx - t0);
+  *out = 1;
+  if (!t->has_out) return INFINITY;
+  return tx + tau / maj[1];
 }
 
 /* ------------------------------------------------------------------ */
@@ -741,25 +855,36 @@ static void photon_woodcock(const orc_ctx *cx, orc_stream *st, double r[3], doub
                             dep_list *l, orc_local *loc)
 {
   const orc_phantom *ph = cx->ph;
+  const int regions = cx->op->tracking == ORC_TRACK_REGIONS;
   double E = ORC_E0_MEV;
   double mur[8][3];
-  double maj = 0.0;
+  double maj[2] = { 0.0, 0.0 }; /* inside the box, outside it */
   double e_cached = -1.0;
   int n_real = 0;
+  int out = regions && !in_box(cx->tab, r); /* in the outer region */
   for (;;) {
     if (E != e_cached) {
       eval_mu_rho(cx->tab, ph->n_mat, E, mur);
-      maj = eval_major(cx->tab, E);
+      maj[0] = eval_major(cx->tab, E);
+      maj[1] = cx->tab->has_out ? cx->tab->out_ratio * maj[0] : 0.0;
       e_cached = E;
     }
     loc->stats[S_STEPS]++;
     loc->rec[5] += 1.0;
-    const double s = -log(stream_uniform(st)) / maj;
-    r[0] += s * d[0];
-    r[1] += s * d[1];
-    r[2] += s * d[2];
+    double s = -log(stream_uniform(st)) / maj[out];
+    if (regions) {
+      const double q[3] = { r[0] + s * d[0], r[1] + s * d[1], r[2] + s * d[2] };
+      if (out || !in_box(cx->tab, q)) s = region_walk(cx->tab, r, d, s, maj, &out);
+    }
+    const int gone = isinf(s); /* left the box with nothing outside it */
+    if (!gone) {
+      r[0] += s * d[0];
+      r[1] += s * d[1];
+      r[2] += s * d[2];
+    }
     const double fx = floor(r[0] / ph->dx), fy = floor(r[1] / ph->dy), fz = floor(r[2] / ph->dz);
-    if (fx < 0.0 || fy < 0.0 || fz < 0.0 || fx >= ph->nx || fy >= ph->ny || fz >= ph->nz) {
+    if (gone || fx < 0.0 || fy < 0.0 || fz < 0.0 || fx >= ph->nx || fy >= ph->ny ||
+        fz >= ph->nz) {
       loc->ledger[L_ESC] += E;
       loc->rec[1] += E;
       loc->stats[S_ESCAPES]++;
@@ -768,7 +893,7 @@ static void photon_woodcock(const orc_ctx *cx, orc_stream *st, double r[3], doub
     const int64_t v = (int64_t)fx + (int64_t)ph->nx * ((int64_t)fy + (int64_t)ph->ny * (int64_t)fz);
     const int m = ph->material[v];
     const double rho = ph->density[v];
-    const double t = stream_uniform(st) * maj;
+    const double t = stream_uniform(st) * maj[out];
     int ev = choose_event(t, rho * mur[m][0], rho * mur[m][1], rho * mur[m][2]);
     if (masked(cx->op, ev)) ev = ORC_EV_NULL;
     if (ev == ORC_EV_NULL) {
@@ -888,7 +1013,7 @@ static void sample_decay(const orc_ctx *cx, orc_stream *st, int64_t iv0[3], doub
 {
   const orc_phantom *ph = cx->ph;
   int64_t v;
-  if (cx->op->tracking == ORC_TRACK_WOODCOCK) {
+  if (cx->op->tracking != ORC_TRACK_EXACT) {
     const uint32_t x = stream_word(st);
     st->n_uniform++;
     (void)stream_uniform(st);
@@ -941,7 +1066,7 @@ static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local 
     }
     loc->ledger[L_EMIT] += ORC_E0_MEV;
     loc->stats[S_PHOTONS]++;
-    if (op->tracking == ORC_TRACK_WOODCOCK)
+    if (op->tracking != ORC_TRACK_EXACT)
       photon_woodcock(cx, &st, r, d, l, loc);
     else
       photon_exact(cx, &st, r, iv, d, l, loc);
@@ -1003,6 +1128,7 @@ int orc_run(const orc_phantom *ph, const orc_opts *op, orc_tally *tal)
       ph->n_mat > 8)
     return -1;
   if (op->photons_per_decay < 1 || op->photons_per_decay > 2) return -1;
+  if (op->tracking < ORC_TRACK_EXACT || op->tracking > ORC_TRACK_REGIONS) return -1;
   if (op->electron_cutoff_mev > 0.0) {
     if (!op->mean_excitation_ev) return -1;
     for (int m = 0; m < ph->n_mat; ++m)

@@ -2,7 +2,11 @@
 attenuation (homogeneous and along a heterogeneous line), first-collision
 energy transfer, a total-absorption cell that fixes the dose units and the
 history-by-history merge, Walters' variance on toy tallies, point-source
-symmetry, and agreement of the two independent tracking modes."""
+symmetry, and agreement of the independent tracking modes.  Tracking 2 is
+Woodcock tracking with a majorant by region (the bounding box of the dense
+voxels and the thin voxels around it): its pins are the same closed forms,
+a beam that starts in the thin region and crosses the box, and agreement
+with exact traversal."""
 import math
 
 import numpy as np
@@ -30,7 +34,7 @@ def _balance(led):
     return (dep + led["escaped"] + led["discarded"]) / led["emitted"] - 1.0
 
 
-@pytest.mark.parametrize("tracking", [0, 1])
+@pytest.mark.parametrize("tracking", [0, 1, 2])
 def test_energy_conservation(orc, tracking):
     prob = P.slab_phantom(n=48, voxel_mm=6.0)
     ph = _oracle_phantom(orc, prob)
@@ -42,7 +46,7 @@ def test_energy_conservation(orc, tracking):
     assert s == pytest.approx(dep, rel=1e-12, abs=0)
 
 
-@pytest.mark.parametrize("tracking", [0, 1])
+@pytest.mark.parametrize("tracking", [0, 1, 2])
 def test_narrow_beam_homogeneous_water(orc, tracking):
     n, h = 25, 4.0  # 10 cm of water
     prob = P.water_point_source(n=n, voxel_mm=h)
@@ -57,7 +61,7 @@ def test_narrow_beam_homogeneous_water(orc, tracking):
     assert abs(uncollided - p) < 4 * math.sqrt(p * (1 - p) / N)
 
 
-@pytest.mark.parametrize("tracking", [0, 1])
+@pytest.mark.parametrize("tracking", [0, 1, 2])
 def test_narrow_beam_through_lung_and_bone(orc, tracking):
     prob = P.slab_phantom()
     ex = prob.extra
@@ -195,6 +199,67 @@ def test_exact_and_woodcock_tracking_agree(orc):
     chi2 = (((da - db) ** 2)[m] / ((da * ea) ** 2 + (db * eb) ** 2)[m]).sum()
     assert stats.chi2.sf(chi2, m.sum()) > 1e-3
     assert abs(_balance(ta.ledger)) < 1e-9 and abs(_balance(tb.ledger)) < 1e-9
+
+
+def test_exact_and_region_tracking_agree(orc):
+    """Exact traversal and Woodcock tracking with region majorants estimate
+    the same dose; the slab's tissue block sits in air, so photons cross the
+    box both ways and interact in both regions."""
+    prob = P.slab_phantom(n=48, voxel_mm=8.0)
+    ph = _oracle_phantom(orc, prob)
+    N = 400000
+    ta, _ = orc.run(ph, N, 61, tracking=0)
+    tb, _ = orc.run(ph, N, 64, tracking=2)
+    ra, sa = orc.organ_mean_sigma(ta, 1.0)
+    rb, sb = orc.organ_mean_sigma(tb, 1.0)
+    z = (ra - rb) / np.sqrt((ra * sa) ** 2 + (rb * sb) ** 2)
+    assert np.all(np.abs(z) < 4.0)
+    da, ea = orc.finalize(ph, ta, 1.0)
+    db, eb = orc.finalize(ph, tb, 1.0)
+    m = (ea > 0) & (eb > 0) & (ea < 0.1) & (eb < 0.1) & (prob.density > 0.01)
+    chi2 = (((da - db) ** 2)[m] / ((da * ea) ** 2 + (db * eb) ** 2)[m]).sum()
+    assert stats.chi2.sf(chi2, m.sum()) > 1e-3
+    # and the air: every voxel's dose there, pooled
+    air = (prob.density < 0.01).ravel()
+    sa_air = float(ta.S.reshape(-1)[air].sum())
+    sb_air = float(tb.S.reshape(-1)[air].sum())
+    va = float(ta.S2.reshape(-1)[air].sum())
+    vb = float(tb.S2.reshape(-1)[air].sum())
+    assert abs(sa_air - sb_air) < 4 * math.sqrt(va + vb)
+    assert abs(_balance(tb.ledger)) < 1e-9
+    # the point of the regions: fewer null collisions for the same histories
+    tw, _ = orc.run(ph, N, 64, tracking=1)
+    assert tb.stats["nulls"] < 0.9 * tw.stats["nulls"]
+    assert tb.stats["histories"] == tw.stats["histories"] == N
+
+
+def test_region_tracking_thin_surroundings(orc):
+    """A pencil beam along a line of voxels: 80 cm of water at 0.009 g/cm^3
+    (thinner than the box threshold, so outside the box), 10 cm of water at
+    unit density (the box), 110 cm of the thin water again.  The beam starts
+    in the thin region, enters the box, and leaves it; interactions in the
+    thin region are real events at the thin density.  The uncollided
+    fraction is exp(-sum mu L) for every tracking mode."""
+    nx = 200
+    density = np.full((1, 1, nx), 0.009)
+    density[0, 0, 80:90] = 1.0
+    material = np.zeros((1, 1, nx), dtype=np.int32)
+    ph = orc.Phantom(density, material, [7.4], [0.5551], (1.0, 1.0, 1.0))
+    mu = _mu(orc, 7.4, 0.5551, 1.0)
+    p = math.exp(-mu * (10.0 + 0.009 * 190.0))
+    N = 200000
+    for tracking, seed in ((0, 71), (1, 72), (2, 73)):
+        tal, rec = orc.run(ph, N, seed, tracking=tracking, photons_per_decay=1,
+                           pencil=((1e-6, 0.5, 0.5), (1.0, 0.0, 0.0)), history_records=True)
+        uncollided = (rec[:, 2] + rec[:, 3] + rec[:, 4] == 0).mean()
+        assert abs(uncollided - p) < 4 * math.sqrt(p * (1 - p) / N), tracking
+        assert abs(_balance(tal.ledger)) < 1e-9
+        # energy deposited in the thin region before the box: first
+        # collisions there happen at rate mu * 0.009 per cm
+        if tracking == 2:
+            first_thin = 1.0 - math.exp(-mu * 0.009 * 80.0)
+            hit_thin = float(tal.S.reshape(-1)[:80].sum()) > 0.0
+            assert hit_thin and first_thin > 0.05
 
 
 def test_organ_score_equals_eq2(orc):
