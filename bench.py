@@ -167,6 +167,10 @@ def main():
     ap.add_argument("--electrons", type=float, default=0.0, metavar="MEV",
                     help="plain MC workloads: walk Compton electrons above this cutoff "
                          "(Section 2.1 uses 0.2 MeV); 0 deposits them on the spot")
+    ap.add_argument("--tracking", choices=("global", "regions"), default="global",
+                    help="plain MC and batch64 workloads: Woodcock majorant for the whole "
+                         "phantom (global) or by region (the box of the dense voxels, and "
+                         "the air around it)")
     ap.add_argument("--phantoms", type=int, default=2,
                     help="organ-time: held-out patients (seeds 20008 onward)")
     ap.add_argument("--weights", default=None,
@@ -242,6 +246,9 @@ def bench_mc(args):
     prob = mc_problem(args.workload)
     eng = B.Engine(0)
     eng.set_problem(0, prob)
+    if args.tracking != "global":
+        B.nmd_set_tracking(eng.ctx, 0, args.tracking)
+        what += "; Woodcock majorants by region"
     if args.electrons > 0:
         iev = [P.MEAN_EXCITATION_EV[next(k for k in P.MATERIALS
                                          if tuple(P.MATERIALS[k][:2]) == tuple(m))]
@@ -306,10 +313,10 @@ def bench_mc(args):
         "config": {"workload": what, "decays_per_step": nd, "decays_per_job": total,
                    "photons_per_decay": prob.photons_per_decay,
                    "electron_cutoff_mev": args.electrons or None,
-                   "tally": "f64", "transport": "f32"},
+                   "tracking": args.tracking, "tally": "f64", "transport": "f32"},
         "roofline": transport_roofline(per_decay, nd, kern_ms,
-                                       None if args.electrons else
-                                       TRAFFIC_BYTES_PER_DECAY.get(args.workload),
+                                       None if args.electrons or args.tracking != "global"
+                                       else TRAFFIC_BYTES_PER_DECAY.get(args.workload),
                                        ceilings),
     }
     if not args.no_cpu:
@@ -389,6 +396,8 @@ def bench_batch(args):
     eng = B.Engine(0)
     for i, p in enumerate(probs):
         eng.set_problem(i, p)
+        if args.tracking != "global":
+            B.nmd_set_tracking(eng.ctx, i, args.tracking)
     # warm-up eager run: tunes the work-queue chunk on the real work
     t0 = time.perf_counter()
     B.nmd_run_histories(eng.ctx, -1, nd, 4001, None)
@@ -440,7 +449,7 @@ def bench_batch(args):
         "config": {"workload": "64 patient phantoms 64..192 x 64..192 x 64..256 voxels of "
                                "2-4 mm, 10^7 decays each per step, hipGraph replay",
                    "voxels": sum(p.nvox for p in probs), "chunk": chunk, "grid_blocks": grid,
-                   "graph_launch_ms": launch_ms},
+                   "graph_launch_ms": launch_ms, "tracking": args.tracking},
         "roofline": transport_roofline(per_decay, nd * len(probs), kern_ms, None,
                                        ceilings),
     }

@@ -162,6 +162,31 @@ nmd_status nmd_set_activity(nmd_ctx *ctx, int32_t phantom_id, const float *activ
 nmd_status nmd_set_electrons(nmd_ctx *ctx, int32_t phantom_id, double cutoff_mev,
                              const double *mean_excitation_ev);
 
+/* Woodcock tracking modes (the free flight of Section 2.1 samples collision
+ * points against a majorant of the attenuation, with null collisions making
+ * up the difference).
+ *   NMD_TRACK_GLOBAL  -- one majorant for the whole phantom (the default).
+ *   NMD_TRACK_REGIONS -- a majorant by region, not in the paper: the
+ *     phantom's inside the inner box, the bounding box of every voxel at
+ *     least 0.01 g/cm^3 dense, and a smaller one in the thinner voxels
+ *     around it (air), the least multiple of the first that bounds them at
+ *     every energy node.  Free flight is memoryless, so a step's optical
+ *     depth is spent region by region along the ray; both modes sample the
+ *     same model, with fewer null collisions here where the phantom sits in
+ *     air.  Each mode draws its own random numbers, so runs of the two modes
+ *     differ history by history and agree in distribution; the oracle's
+ *     region mode replays this one.
+ * The mode selects a separate instantiation of the transport kernel; a
+ * batched run that holds a phantom in region mode runs them all in it
+ * (phantoms in global mode, and phantoms whose box is the whole grid, see
+ * one region there and draw as under NMD_TRACK_GLOBAL).  The tallies are
+ * kept; graphs captured before the change refuse to launch (NMD_E_STATE);
+ * re-registering the phantom returns it to NMD_TRACK_GLOBAL; checkpoints do
+ * not record the mode.  Errors: NMD_E_STATE (phantom not registered),
+ * NMD_E_INVALID (mode).  Synchronises the stream. */
+enum { NMD_TRACK_GLOBAL = 0, NMD_TRACK_REGIONS = 1 };
+nmd_status nmd_set_tracking(nmd_ctx *ctx, int32_t phantom_id, int32_t mode);
+
 /* ---- transport ----------------------------------------------------------- */
 
 /* Simulate n_decays histories of phantom `phantom_id`, or of every phantom

@@ -82,7 +82,7 @@ EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
            "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
            "nmd_graph_launch", "nmd_graph_destroy", "nmd_save", "nmd_load",
-           "nmd_set_electrons") + NN_EXPORTS + INGEST_EXPORTS + \
+           "nmd_set_electrons", "nmd_set_tracking") + NN_EXPORTS + INGEST_EXPORTS + \
     PROBE_EXPORTS
 
 _lib = None
@@ -127,6 +127,7 @@ def load_library(path: str = LIB_PATH):
         "nmd_graph_launch": [vp],
         "nmd_save": [vp, i32, ctypes.c_char_p],
         "nmd_set_electrons": [vp, i32, d, vp],
+        "nmd_set_tracking": [vp, i32, i32],
         "nmd_load": [vp, i32, ctypes.c_char_p],
         "nmd_graph_destroy": [vp],
         "nmd_conv3d_fwd": [vp, i32, i32, i32, i32, ctypes.POINTER(nmd_nn_src), vp, vp, i32, i32,
@@ -280,6 +281,15 @@ def nmd_set_electrons(ctx, phantom_id, cutoff_mev, mean_excitation_ev=None):
     _check(ctx, load_library().nmd_set_electrons(
         ctx, int(phantom_id), float(cutoff_mev),
         None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)))
+
+
+TRACKING = {"global": 0, "regions": 1}
+
+
+def nmd_set_tracking(ctx, phantom_id, mode):
+    """mode: "global" / "regions" (or NMD_TRACK_* numbers)."""
+    m = TRACKING[mode] if isinstance(mode, str) else int(mode)
+    _check(ctx, load_library().nmd_set_tracking(ctx, int(phantom_id), m))
 
 
 def nmd_save(ctx, phantom_id, path):

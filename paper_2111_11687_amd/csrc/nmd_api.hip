@@ -76,6 +76,9 @@ struct Phantom {
   int n_mat = 0;
   std::vector<double> mat_zoa;  // Z/A of each material
   DevBuf e_tab, e_inv_dr, e_slot;  // electron range tables (nmd_set_electrons)
+  int32_t box0[3] = {0, 0, 0}, box1[3] = {0, 0, 0};  // inner box, voxel indices [box0, box1)
+  double out_ratio = 0.0;  // outer majorant / inner majorant (0: no outer region)
+  int32_t tracking = NMD_TRACK_GLOBAL;  // NMD_TRACK_* (nmd_set_tracking)
   float e_cut = 0.0f, e_inv_dt = 0.0f;
   uint64_t geom_hash = 0;   // FNV-1a of the voxel records, for checkpoints
   uint64_t act_hash = 0;    // FNV-1a of the alias table, for checkpoints
@@ -269,6 +272,21 @@ PhantomDesc make_desc(int32_t id, const Phantom &p) {
   d.inv_dz = (float)(1.0 / p.dz);
   d.n_alias = p.n_alias;
   d.pid = (uint32_t)id;
+  // region tracking: the inner box and the outer majorant ratio; under
+  // global tracking (or without an outer region) the box is the whole grid
+  // and the ratio 0, which the region-tracking kernel reads as one region
+  const bool regions = p.tracking == NMD_TRACK_REGIONS && p.out_ratio > 0.0;
+  const double h[3] = {p.dx, p.dy, p.dz};
+  const int32_t n[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; ++a) {
+    const int32_t lo = regions ? p.box0[a] : 0, hi = regions ? p.box1[a] : n[a];
+    d.b0[a] = (float)lo;
+    d.b1[a] = (float)hi;
+    d.bcm0[a] = (float)(lo * h[a]);
+    d.bcm1[a] = (float)(hi * h[a]);
+  }
+  d.out_ratio = regions ? (float)p.out_ratio : 0.0f;
+  d.inv_out_ratio = regions ? (float)(1.0 / p.out_ratio) : 0.0f;
   d.e_tab = p.e_tab.as<float>();
   d.e_inv_dr = p.e_inv_dr.as<float>();
   d.e_slot = p.e_slot.as<uint8_t>();
@@ -323,6 +341,7 @@ struct RunPlan {
   int grid = 0;
   bool debug = false;
   bool electrons = false;   // some phantom of the run walks its Compton electrons
+  bool regions = false;     // some phantom of the run has region majorants
   bool auto_chunk = false;  // caller asked for the tuned chunk
   bool tuned = false;       // a tuned chunk was known
   uint32_t abort_after = 0;
@@ -419,7 +438,12 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
   pl.debug = o.history_records != nullptr;
   pl.electrons = false;
   for (int32_t i : ids) pl.electrons = pl.electrons || c->ph[i].e_cut > 0.0f;
-  const int per_cu = transport_occupancy_blocks_per_cu(pl.debug, pl.electrons, n_slots);
+  pl.regions = false;
+  for (int32_t i : ids)
+    pl.regions = pl.regions ||
+                 (c->ph[i].tracking == NMD_TRACK_REGIONS && c->ph[i].out_ratio > 0.0);
+  const int per_cu =
+      transport_occupancy_blocks_per_cu(pl.debug, pl.electrons, pl.regions, n_slots);
   uint32_t grid = o.grid_blocks ? o.grid_blocks : (uint32_t)(c->cu_count * per_cu);
   grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, 8192));
   pl.grid = (int)grid;
@@ -435,6 +459,7 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
     c->dep_lanes = lanes;
   }
   pl.key = tune_key(c, ids);
+  if (pl.regions) pl.key += "|regions";
   pl.auto_chunk = o.chunk == 0;
   uint32_t chunk = o.chunk;
   if (chunk == 0) {
@@ -492,7 +517,7 @@ nmd_status enqueue_run(nmd_ctx *c, RunPlan &pl, unsigned long long *queue, uint3
   pl.rp.dep_e = dep_e;
   pl.rp.dep_r = dep_r;
   HIP_TRY(c, launch_zero_bytes(queue, 2 * sizeof(unsigned long long), st));
-  HIP_TRY(c, launch_transport(pl.rp, pl.grid, pl.debug, pl.electrons, st));
+  HIP_TRY(c, launch_transport(pl.rp, pl.grid, pl.debug, pl.electrons, pl.regions, st));
   if (!advance) return NMD_OK;
   uint64_t n = pl.rp.n_ph ? pl.rp.slot[0].n_hist : 0;
   HIP_TRY(c, launch_advance(pl.rp.desc, pl.ids, n, st));
@@ -833,6 +858,57 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
     }
     maj[i] = round_up_f32(std::log2(mx));
   }
+  // the inner box: the bounding box of the voxels at least kInnerRho dense;
+  // the (material, density) pairs outside it set the outer majorant
+  int32_t b0[3] = {nx, ny, nz}, b1[3] = {0, 0, 0};
+  for (int32_t k = 0, v = 0; k < nz; ++k)
+    for (int32_t j = 0; j < ny; ++j)
+      for (int32_t i = 0; i < nx; ++i, ++v)
+        if (h_rho[v] >= kInnerRho) {
+          b0[0] = std::min(b0[0], i);
+          b0[1] = std::min(b0[1], j);
+          b0[2] = std::min(b0[2], k);
+          b1[0] = std::max(b1[0], i + 1);
+          b1[1] = std::max(b1[1], j + 1);
+          b1[2] = std::max(b1[2], k + 1);
+        }
+  if (b1[0] == 0) {  // nothing that dense: one region, the whole grid
+    b0[0] = b0[1] = b0[2] = 0;
+    b1[0] = nx;
+    b1[1] = ny;
+    b1[2] = nz;
+  }
+  std::vector<uint8_t> used_out(kMaxPalette, 0);
+  bool any_out = false;
+  for (int32_t k = 0, v = 0; k < nz; ++k)
+    for (int32_t j = 0; j < ny; ++j)
+      for (int32_t i = 0; i < nx; ++i, ++v)
+        if (i < b0[0] || i >= b1[0] || j < b0[1] || j >= b1[1] || k < b0[2] || k >= b1[2]) {
+          used_out[rec[v] & 0xFFu] = 1;
+          any_out = true;
+        }
+  // the outer majorant is out_ratio times the inner one: the largest ratio,
+  // over the energy nodes, of the outer voxels' attenuation to the inner
+  // majorant node (log-log interpolation keeps the bound between nodes),
+  // widened by 2^-16 for the FP32 product
+  double ratio = 0.0;
+  for (int i = 0; any_out && i < kNGrid; ++i) {
+    const double e = grid_e(i);
+    const double s_na = kNA * sigma_kn(e);
+    double mx = 0.0;
+    for (size_t q = 0; q < pal.size(); ++q) {
+      if (!used_out[q]) continue;
+      double cc, cpe, cr;
+      pal_coeffs(pal[q].z, pal[q].zoa, (double)pal[q].rho, cc, cpe, cr);
+      mx = std::max(mx, cc * s_na + cpe / (e * e * e) + cr / (e * e));
+    }
+    ratio = std::max(ratio, mx / std::exp2((double)maj[i]));
+  }
+  p.out_ratio = any_out ? ratio * (1.0 + 1.0 / 65536.0) : 0.0;
+  for (int a = 0; a < 3; ++a) {
+    p.box0[a] = b0[a];
+    p.box1[a] = b1[a];
+  }
   std::vector<double> ow(n_organs + 1, 0.0);
   for (int o = 0; o <= n_organs; ++o)
     ow[o] = count[o] > 0 ? kJPerMeV / (p.vkg() * (double)count[o]) : 0.0;
@@ -852,6 +928,7 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
                             c->stream));
   HIP_TRY(c, hipMemcpyAsync(p.major.p, maj.data(), kNGrid * sizeof(float), hipMemcpyHostToDevice,
                             c->stream));
+
   HIP_TRY(c, hipMemcpyAsync(p.organ_w.p, ow.data(), ow.size() * sizeof(double),
                             hipMemcpyHostToDevice, c->stream));
   std::vector<float4> pal_dev(pal.size());
@@ -976,6 +1053,20 @@ nmd_status nmd_set_electrons(nmd_ctx *c, int32_t id, double cutoff_mev,
   }
   p->gen = c->next_gen++;
   if (p->has_activity && (s = zero_tallies(c, *p))) return s;
+  return upload_desc(c, id, *p);
+}
+
+nmd_status nmd_set_tracking(nmd_ctx *c, int32_t id, int32_t mode) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (mode != NMD_TRACK_GLOBAL && mode != NMD_TRACK_REGIONS)
+    return fail(c, NMD_E_INVALID, "tracking mode must be NMD_TRACK_GLOBAL or NMD_TRACK_REGIONS");
+  p->tracking = mode;
+  // the same model either way, so the tallies stay; graphs captured with
+  // the other kernel no longer match
+  p->gen = c->next_gen++;
   return upload_desc(c, id, *p);
 }
 

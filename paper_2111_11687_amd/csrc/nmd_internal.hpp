@@ -27,6 +27,7 @@ constexpr int kOrgCache = 3;              // organ score slots per history, in r
 constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
 constexpr int kETab = 256;                // nodes of the electron range and inverse-range tables
 constexpr int kMaxMaterials = 8;
+constexpr float kInnerRho = 0.01f;        // g/cm^3: voxels at least this dense lie in the inner box
 
 // Workgroups of the transport kernel the compiler must fit on one CU (it
 // caps registers accordingly); a build-time tuning knob.
@@ -66,6 +67,15 @@ struct PhantomDesc {
   // spot) walk straight ahead through the grid: per material slot s the
   // CSDA range above the cutoff R_s(T) (g/cm^2) on the nodes
   // T_i = e_cut + i / e_inv_dt, and its inverse T_s(R) on R_j = j / inv_dr_s
+  // Woodcock majorants by region (region tracking): inside the inner box
+  // (the bounding box of every voxel at least kInnerRho dense; voxel units
+  // [b0, b1), and in cm) the phantom's majorant, elsewhere in the grid (only
+  // thinner voxels) out_ratio times it, the smallest ratio that bounds those
+  // voxels at every energy.  out_ratio is 0 under global tracking, and when
+  // the box is the whole grid.
+  float b0[3], b1[3];
+  float bcm0[3], bcm1[3];
+  float out_ratio, inv_out_ratio;
   const float *e_tab;    // [kMaxMaterials][2][kETab]: R_s(T_i), then T_s(R_j)
   const float *e_inv_dr; // [kMaxMaterials]
   const uint8_t *e_slot; // [kMaxPalette]: palette index -> material slot
@@ -119,9 +129,11 @@ struct RunParams {
   RunSlot slot[kMaxPhantoms];
 };
 
+// regions: the instantiation with region majorants, needed when a phantom of
+// the run has a nonzero out_ratio
 hipError_t launch_transport(const RunParams &p, int grid, bool debug, bool electrons,
-                            hipStream_t s);
-int transport_occupancy_blocks_per_cu(bool debug, bool electrons, int n_slots);
+                            bool regions, hipStream_t s);
+int transport_occupancy_blocks_per_cu(bool debug, bool electrons, bool regions, int n_slots);
 size_t transport_dyn_lds_bytes(int n_slots);
 hipError_t launch_finalize(const uint16_t *rec, const float4 *palette, const double2 *tally,
                            uint64_t nvox, const unsigned long long *n_decays,

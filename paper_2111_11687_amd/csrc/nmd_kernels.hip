@@ -110,7 +110,7 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <bool kDebug, bool kElectrons>
+template <bool kDebug, bool kElectrons, bool kRegions>
 __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_kernel(RunParams P) {
   __shared__ float4 s_pal[kMaxPalette];
   __shared__ double s_irho[kMaxPalette];  // 1 / density, for the organ scores
@@ -163,6 +163,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
 
   // lane state: which phase the lane waits for
   constexpr uint32_t kIdle = 0, kFlight = 1, kInteract = 2, kPhotonEnd = 3;
+  // bit of psteps set while the photon is outside the inner box (region
+  // tracking)
+  constexpr uint32_t kOuter = 0x80000000u;
+  static_assert(kMaxPhotonSteps < kOuter, "step counter and region bit");
   uint32_t state = kIdle;
   uint32_t ev_v = 0, ev_r = 0;  // pending interaction: voxel and its record
   int ev_t = 0;                 // 1 Compton, 2 photoelectric, 3 Rayleigh
@@ -262,6 +266,78 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     ep.gr = wa.ep0[2];
     ep.mu_hat = wa.ep0[3];
     ep.inv_mu_ln2 = wa.ep0[4];
+    if (kRegions) {
+      const float fx = px * D->inv_dx, fy = py * D->inv_dy, fz = pz * D->inv_dz;
+      if (D->out_ratio > 0.0f &&
+          !(fx >= D->b0[0] && fx < D->b1[0] && fy >= D->b0[1] && fy < D->b1[1] &&
+            fz >= D->b0[2] && fz < D->b1[2])) {
+        // a decay outside the inner box: its photons start in the outer region
+        psteps = kOuter;
+        ep.mu_hat *= D->out_ratio;
+        ep.inv_mu_ln2 *= D->inv_out_ratio;
+      }
+    }
+  };
+
+  // Region tracking.  One Woodcock step of path length s, drawn with the
+  // current region's majorant, that leaves the inner box or starts outside
+  // it.  The majorant is piecewise constant along the ray -- the phantom's
+  // inside the box, out_ratio times that outside it -- so the step's optical
+  // depth is spent region by region (free flight is memoryless).  Returns
+  // the path length to the step's end point and sets the region bit and
+  // ep.mu_hat / ep.inv_mu_ln2 to the end point's region.  Without an outer
+  // region a ray leaving the box leaves the grid.
+  //
+  // From inside (photons on their way out of the body), the ray leaves at
+  // the box's exit distance tf and the rest of the step stretches by
+  // 1 / out_ratio.
+  auto box_exit = [&](float s) -> float {
+    CDesc *d = D;
+    const float p[3] = {px, py, pz}, u[3] = {ux, uy, uz};
+    float tf = 3.0e38f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float b = u[a] > 0.0f ? d->bcm1[a] : d->bcm0[a];
+      const float ta = u[a] != 0.0f ? (b - p[a]) / u[a] : 3.0e38f;
+      tf = fminf(tf, fmaxf(ta, 0.0f));
+    }
+    psteps |= kOuter;
+    ep.mu_hat *= d->out_ratio;
+    ep.inv_mu_ln2 *= d->inv_out_ratio;
+    return d->out_ratio > 0.0f ? tf + (s - tf) * d->inv_out_ratio : 3.0e38f;
+  };
+  // From outside (photons that started or interacted in the thin outer
+  // region): the ray crosses the convex box along one interval [tn, tf] of
+  // its parameter, if at all, found once from the start point.
+  auto region_step = [&](float s) -> float {
+    CDesc *d = D;
+    const float p[3] = {px, py, pz}, u[3] = {ux, uy, uz};
+    const float mu_out = ep.mu_hat, mu_in = ep.mu_hat * d->inv_out_ratio;
+    float tau = s * mu_out;
+    float tn = -3.0e38f, tf = 3.0e38f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (u[a] != 0.0f) {
+        const float t1 = (d->bcm0[a] - p[a]) / u[a], t2 = (d->bcm1[a] - p[a]) / u[a];
+        tn = fmaxf(tn, fminf(t1, t2));
+        tf = fminf(tf, fmaxf(t1, t2));
+      } else if (!(p[a] >= d->bcm0[a] && p[a] < d->bcm1[a])) {
+        tf = -3.0e38f;
+      }
+    }
+    const float te = fmaxf(tn, 0.0f);
+    // a ray that misses the box, or only touches it, stays outside
+    if (!(tn < tf) || !(tf > 0.0f) || tau <= mu_out * te) return s;
+    tau -= mu_out * te;
+    const float tx = fmaxf(tf, te);  // where the ray leaves the box again
+    if (tau <= mu_in * (tx - te)) {
+      psteps &= ~kOuter;
+      ep.mu_hat = mu_in;
+      ep.inv_mu_ln2 *= d->out_ratio;
+      return te + tau / mu_in;
+    }
+    tau -= mu_in * (tx - te);
+    return tx + tau / mu_out;
   };
 
   auto start_history = [&](unsigned long long rel) {
@@ -789,6 +865,10 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
               pdone = true;
             } else {
               ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+              if (kRegions && (psteps & kOuter)) {  // a Compton event outside the inner box
+                ep.mu_hat *= D->out_ratio;
+                ep.inv_mu_ln2 *= D->inv_out_ratio;
+              }
               if (walked) dep = -1.0;  // nothing left at the event point
             }
           } else if (ev_t == 2) {
@@ -874,11 +954,13 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         // record is read: the records are gathered together, and a step's
         // outcome is used only after null collisions on the steps before
         // it.  Arithmetic and draws are those of taking the steps one by one.
+        // (Under region tracking a step's majorant depends on the region the
+        // previous step ended in: there the steps go one by one.)
         const uint32_t w_len[2] = {st.b0, st.b2};  // each step's length word
         float qx[kFlySteps], qy[kFlySteps], qz[kFlySteps];
         bool qin[kFlySteps];
         uint32_t qv[kFlySteps], qr[kFlySteps];
-        {
+        if (!kRegions) {
           float cx = px, cy = py, cz = pz;
 #pragma unroll
           for (int k = 0; k < kFlySteps; ++k) {
@@ -908,17 +990,46 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
           if (state != kFlight) break;
           if (kDebug) ++h_steps;
           ++ns;
-          (void)st.take();  // the step's length word, used above
-          px = qx[k];
-          py = qy[k];
-          pz = qz[k];
+          if (kRegions) {
+            float s = -fast_log2(st.take_uniform()) * ep.inv_mu_ln2;
+            float fx = (px + s * ux) * D->inv_dx, fy = (py + s * uy) * D->inv_dy,
+                  fz = (pz + s * uz) * D->inv_dz;
+            // inside the inner box (which lies in the grid), written so that
+            // a NaN coordinate counts as outside; a step that leaves the box
+            // or starts outside it takes the region walk
+            bool in = true;
+            if (!(fx >= D->b0[0] && fx < D->b1[0] && fy >= D->b0[1] && fy < D->b1[1] &&
+                  fz >= D->b0[2] && fz < D->b1[2]) ||
+                (psteps & kOuter)) {
+              s = (psteps & kOuter) ? region_step(s) : box_exit(s);
+              fx = (px + s * ux) * D->inv_dx;
+              fy = (py + s * uy) * D->inv_dy;
+              fz = (pz + s * uz) * D->inv_dz;
+              in = fx >= 0.0f && fx < D->fnx && fy >= 0.0f && fy < D->fny && fz >= 0.0f &&
+                   fz < D->fnz;
+            }
+            px += s * ux;
+            py += s * uy;
+            pz += s * uz;
+            qin[k] = in;
+            qv[k] = in ? (uint32_t)fx + (uint32_t)D->nx *
+                                            ((uint32_t)fy + (uint32_t)D->ny * (uint32_t)fz)
+                       : 0u;
+            qr[k] = in ? (uint32_t)G(D->rec)[qv[k]] : 0u;
+            ng += in ? 1u : 0u;
+          } else {
+            (void)st.take();  // the step's length word, used above
+            px = qx[k];
+            py = qy[k];
+            pz = qz[k];
+          }
           if (!qin[k]) {
             atomicAdd(&wa.ledger[4], (double)E);
             if (kDebug) h_pe_esc += 0x10000u;
             ++ne;
             if (kDebug) h_esc += E;
             state = kPhotonEnd;
-          } else if (++psteps > kMaxPhotonSteps) {
+          } else if ((++psteps & ~kOuter) > kMaxPhotonSteps) {
             // unreachable for valid input; bounds the loop for any input
             atomicAdd(&wa.ledger[5], (double)E);
             if (kDebug) h_disc += E;
@@ -976,30 +1087,28 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   flush_wave();
 }
 
-int transport_occupancy_blocks_per_cu(bool debug, bool electrons, int n_slots) {
+typedef void (*TransportFn)(RunParams);
+
+static TransportFn transport_fn(bool debug, bool electrons, bool regions) {
+  static const TransportFn fn[8] = {
+      transport_kernel<false, false, false>, transport_kernel<false, false, true>,
+      transport_kernel<false, true, false>,  transport_kernel<false, true, true>,
+      transport_kernel<true, false, false>,  transport_kernel<true, false, true>,
+      transport_kernel<true, true, false>,   transport_kernel<true, true, true>};
+  return fn[(debug ? 4 : 0) + (electrons ? 2 : 0) + (regions ? 1 : 0)];
+}
+
+int transport_occupancy_blocks_per_cu(bool debug, bool electrons, bool regions, int n_slots) {
   int nb = 0;
-  const size_t dyn = transport_dyn_lds_bytes(n_slots);
-  hipError_t e;
-  if (debug)
-    e = electrons ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true, true>, kBlock, dyn)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<true, false>, kBlock, dyn);
-  else
-    e = electrons ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false, true>, kBlock, dyn)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_kernel<false, false>, kBlock, dyn);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &nb, transport_fn(debug, electrons, regions), kBlock, transport_dyn_lds_bytes(n_slots));
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 hipError_t launch_transport(const RunParams &p, int grid, bool debug, bool electrons,
-                            hipStream_t s) {
-  const size_t dyn = transport_dyn_lds_bytes(p.n_slots);
-  if (debug && electrons)
-    hipLaunchKernelGGL((transport_kernel<true, true>), dim3(grid), dim3(kBlock), dyn, s, p);
-  else if (debug)
-    hipLaunchKernelGGL((transport_kernel<true, false>), dim3(grid), dim3(kBlock), dyn, s, p);
-  else if (electrons)
-    hipLaunchKernelGGL((transport_kernel<false, true>), dim3(grid), dim3(kBlock), dyn, s, p);
-  else
-    hipLaunchKernelGGL((transport_kernel<false, false>), dim3(grid), dim3(kBlock), dyn, s, p);
+                            bool regions, hipStream_t s) {
+  hipLaunchKernelGGL(transport_fn(debug, electrons, regions), dim3(grid), dim3(kBlock),
+                     transport_dyn_lds_bytes(p.n_slots), s, p);
   return hipGetLastError();
 }
 
