@@ -26,7 +26,8 @@ KN_KAHN, KN_BUTCHER = 0, 1
 RNG_PHILOX, RNG_XOSHIRO = 0, 1
 SRC_ACTIVITY, SRC_PENCIL = 0, 1
 
-LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded")
+LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded",
+                 "dep_positron")
 STATS_FIELDS = ("histories", "photons", "steps", "nulls", "compton", "photoelectric",
                 "rayleigh", "deposits", "merged", "max_merged", "escapes", "uniforms")
 HREC_FIELDS = ("edep", "escaped", "n_compton", "n_pe", "n_rayleigh", "n_steps",
@@ -65,12 +66,13 @@ class _Opts(ctypes.Structure):
                 ("pencil_origin", ctypes.c_double * 3), ("pencil_dir", ctypes.c_double * 3),
                 ("n_threads", ctypes.c_int32), ("hist_out", ctypes.c_void_p),
                 ("electron_cutoff_mev", ctypes.c_double),
-                ("mean_excitation_ev", ctypes.c_void_p), ("rng", ctypes.c_int32)]
+                ("mean_excitation_ev", ctypes.c_void_p), ("rng", ctypes.c_int32),
+                ("positron", ctypes.c_int32), ("noncol_fwhm_rad", ctypes.c_double)]
 
 
 class _Tally(ctypes.Structure):
     _fields_ = [("S", ctypes.c_void_p), ("S2", ctypes.c_void_p), ("O", ctypes.c_void_p),
-                ("O2", ctypes.c_void_p), ("ledger", ctypes.c_double * 6),
+                ("O2", ctypes.c_void_p), ("ledger", ctypes.c_double * 7),
                 ("stats", ctypes.c_uint64 * 12)]
 
 
@@ -117,6 +119,8 @@ def lib():
         for name in ("orc_stopping_power",):
             getattr(L, name).restype = d
             getattr(L, name).argtypes = [d, d, d]
+        L.orc_beta_plus_shape.restype = d
+        L.orc_beta_plus_shape.argtypes = [d]
         L.orc_csda_range.restype = d
         L.orc_csda_range.argtypes = [d, d, d, d]
         L.orc_energy_after.restype = d
@@ -159,13 +163,15 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-_SAMPLE_WIDTH = {0: 4, 1: 1, 2: 3, 3: 2, 4: 2, 5: 1}
+_SAMPLE_WIDTH = {0: 4, 1: 1, 2: 3, 3: 2, 4: 2, 5: 1, 6: 1, 7: 1}
 
 
 def sample(kind: str, n: int, seed: int = 1, e_mev: float = 0.511,
            wide: bool = False, rng: int = RNG_PHILOX) -> np.ndarray:
-    """Draw n samples; kind in {'raw','uniform','marsaglia','kahn','butcher','thomson'}."""
-    k = {"raw": 0, "uniform": 1, "marsaglia": 2, "kahn": 3, "butcher": 4, "thomson": 5}[kind]
+    """Draw n samples; kind in {'raw','uniform','marsaglia','kahn','butcher','thomson',
+    'positron_energy','noncollinear'} (for 'noncollinear', e_mev is the FWHM in rad)."""
+    k = {"raw": 0, "uniform": 1, "marsaglia": 2, "kahn": 3, "butcher": 4, "thomson": 5,
+         "positron_energy": 6, "noncollinear": 7}[kind]
     out = np.zeros(n * _SAMPLE_WIDTH[k], dtype=np.float64)
     rc = lib().orc_sample(k, float(e_mev), int(n), int(seed), int(wide), int(rng), _ptr(out))
     if rc != 0:
@@ -312,7 +318,8 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
         process_mask: int = 7, max_real_events: int = 0, cutoff_mev: float = 0.010,
         tracking: int = TRACK_EXACT, kn_method: int | None = None, wide: bool | None = None,
         pencil=None, n_threads: int = 0, history_records: bool = False,
-        electron_cutoff_mev: float = 0.0, mean_excitation_ev=None, rng: int | None = None):
+        electron_cutoff_mev: float = 0.0, mean_excitation_ev=None, rng: int | None = None,
+        positron: bool = False, noncol_fwhm_deg: float = 0.5):
     """Run n_hist histories; returns (tally, per-history records or None).
 
     ``pencil=(origin_cm, direction)`` selects a pencil-beam source.  The
@@ -321,7 +328,11 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
     does not use); Woodcock replays the device draw order (Philox4x32-10,
     Butcher-Messel, 23-bit uniforms).  ``electron_cutoff_mev > 0`` walks Compton electrons
     above it straight ahead (CSDA; needs ``mean_excitation_ev`` per
-    material); 0 deposits them on the spot.
+    material); 0 deposits them on the spot.  ``positron=True`` gives each
+    decay its 18F positron (kinetic energy from the beta+ spectrum, a
+    straight CSDA walk, the pair born where it ends; needs
+    ``mean_excitation_ev``) and tilts the second photon off back to back by
+    a Rayleigh-distributed angle of FWHM ``noncol_fwhm_deg``.
     """
     if tally is None:
         tally = Tally(ph)
@@ -350,14 +361,17 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
     o.n_threads = n_threads
     o.hist_out = _ptr(rec)
     iev = None
-    if electron_cutoff_mev > 0.0:
+    if electron_cutoff_mev > 0.0 or positron:
         if mean_excitation_ev is None:
-            raise ValueError("electron transport needs mean_excitation_ev per material")
+            raise ValueError("electron and positron transport need mean_excitation_ev per "
+                             "material")
         iev = np.ascontiguousarray(mean_excitation_ev, dtype=np.float64)
         if iev.shape != (len(ph.z_eff),):
             raise ValueError("one mean excitation energy per material")
     o.electron_cutoff_mev = float(electron_cutoff_mev)
     o.mean_excitation_ev = _ptr(iev)
+    o.positron = int(bool(positron))
+    o.noncol_fwhm_rad = float(np.radians(noncol_fwhm_deg))
     rc = lib().orc_run(ctypes.byref(ph._c), ctypes.byref(o), ctypes.byref(tally._c))
     if rc != 0:
         raise ValueError("oracle rejected the input (code %d)" % rc)

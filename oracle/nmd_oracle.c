@@ -70,7 +70,15 @@
 #define ORC_ZREF 7.4                      /* anchor Z                   */
 #define ORC_KAPPA (1.0 + 1.0 / 16384.0)   /* majorant inflation         */
 
-#define ORC_LEDGER_N 6
+/* 18F positrons (the emitter of Section 2.1): the beta+ endpoint kinetic
+ * energy (MeV) and the charge of the daughter nucleus (18O). */
+#define ORC_F18_T0 0.6335
+#define ORC_F18_ZD 8.0
+#define ORC_ALPHA (1.0 / 137.035999084) /* fine-structure constant */
+#define ORC_POS_FLOOR 0.001 /* MeV: a positron's walk ends when its range above this runs out */
+#define ORC_POS_CDF_N 4096  /* intervals of the tabulated spectrum CDF */
+
+#define ORC_LEDGER_N 7
 #define ORC_STATS_N 12
 #define ORC_HREC_N 10
 
@@ -79,7 +87,7 @@ enum { ORC_KN_KAHN = 0, ORC_KN_BUTCHER = 1 };
 enum { ORC_SRC_ACTIVITY = 0, ORC_SRC_PENCIL = 1 };
 enum { ORC_EV_NULL = 0, ORC_EV_COMPTON = 1, ORC_EV_PE = 2, ORC_EV_RAYLEIGH = 3 };
 /* ledger slots */
-enum { L_EMIT = 0, L_DEP_C = 1, L_DEP_PE = 2, L_DEP_CUT = 3, L_ESC = 4, L_DISC = 5 };
+enum { L_EMIT = 0, L_DEP_C = 1, L_DEP_PE = 2, L_DEP_CUT = 3, L_ESC = 4, L_DISC = 5, L_DEP_POS = 6 };
 /* stats slots */
 enum {
   S_HIST = 0, S_PHOTONS = 1, S_STEPS = 2, S_NULL = 3, S_COMPTON = 4, S_PE = 5,
@@ -412,6 +420,10 @@ typedef struct {
                                      electrons above it walk straight ahead (CSDA) */
   const double *mean_excitation_ev; /* [n_mat], eV; needed when the cutoff is > 0 */
   int32_t rng;                    /* ORC_RNG_PHILOX or ORC_RNG_XOSHIRO */
+  int32_t positron;               /* 0: the photon pair starts at the decay point, exactly
+                                     back to back; 1: 18F positron range and non-collinearity
+                                     (needs mean_excitation_ev) */
+  double noncol_fwhm_rad;         /* FWHM of the pair's deviation from back to back */
 } orc_opts;
 
 /* Accumulators.  S, S2: [nvox]; O, O2: [n_organs + 1]; all caller-owned
@@ -613,6 +625,7 @@ typedef struct {
   const int64_t *n_org; /* voxels per organ label */
   const double *cdf;    /* source CDF over voxels */
   int64_t nvox;
+  const double *pos_cdf; /* positron spectrum CDF on ORC_POS_CDF_N + 1 nodes, or NULL */
 } orc_ctx;
 
 /* One photon in the exact-traversal mode.  Returns via the deposit list
@@ -705,12 +718,14 @@ double orc_energy_after(double t, double p, double t_floor, double z_over_a, dou
  * voxel it loses what its mass path rho * s takes off the range; in the
  * voxel where the range above the cutoff runs out it leaves all it still
  * has.  Calls dep(v, e) per voxel; returns the energy carried out of the
- * grid. */
+ * grid.  end (may be NULL) receives the point where the range runs out
+ * (positrons annihilate there); a walk that leaves the grid sets it to the
+ * exit point. */
 typedef void (*orc_dep_fn)(void *user, int64_t v, double e);
 
 static double electron_walk(const orc_phantom *ph, const double *i_ev, double cutoff,
                             const double r[3], const int64_t iv_in[3], const double de[3],
-                            double t0, orc_dep_fn dep, void *user)
+                            double t0, orc_dep_fn dep, void *user, double *end)
 {
   const int32_t n[3] = { ph->nx, ph->ny, ph->nz };
   const double h[3] = { ph->dx, ph->dy, ph->dz };
@@ -743,8 +758,11 @@ static double electron_walk(const orc_phantom *ph, const double *i_ev, double cu
     if (tnext[1] < tnext[ax]) ax = 1;
     if (tnext[2] < tnext[ax]) ax = 2;
     const double seg = tnext[ax] - s_cur;
-    if (rho * seg >= orc_csda_range(cutoff, t, za, ie)) {
+    const double rng = orc_csda_range(cutoff, t, za, ie);
+    if (rho * seg >= rng) {
       dep(user, v, t);
+      if (end)
+        for (int a = 0; a < 3; ++a) end[a] = r[a] + (s_cur + rng / rho) * de[a];
       return 0.0;
     }
     const double t1 = orc_energy_after(t, rho * seg, cutoff, za, ie);
@@ -753,7 +771,11 @@ static double electron_walk(const orc_phantom *ph, const double *i_ev, double cu
     s_cur = tnext[ax];
     iv[ax] += stp[ax];
     tnext[ax] += tstep[ax];
-    if (iv[ax] < 0 || iv[ax] >= n[ax]) return t;
+    if (iv[ax] < 0 || iv[ax] >= n[ax]) {
+      if (end)
+        for (int a = 0; a < 3; ++a) end[a] = r[a] + s_cur * de[a];
+      return t;
+    }
   }
 }
 
@@ -761,12 +783,13 @@ static double electron_walk(const orc_phantom *ph, const double *i_ev, double cu
 typedef struct {
   dep_list *l;
   orc_local *loc;
+  int slot; /* ledger slot of the deposits */
 } walk_sink;
 
 static void walk_deposit(void *user, int64_t v, double e)
 {
   walk_sink *w = (walk_sink *)user;
-  add_dep(w->l, w->loc, v, e, L_DEP_C);
+  add_dep(w->l, w->loc, v, e, w->slot);
 }
 
 /* The Compton electron of energy te at position r in voxel v: deposited on
@@ -790,9 +813,9 @@ static void compton_electron(const orc_ctx *cx, int64_t v, const double r[3], co
   }
   for (int a = 0; a < 3; ++a) p[a] /= pn;
   const int64_t iv[3] = { v % ph->nx, (v / ph->nx) % ph->ny, v / ((int64_t)ph->nx * ph->ny) };
-  walk_sink sink = { l, loc };
+  walk_sink sink = { l, loc, L_DEP_C };
   const double esc = electron_walk(ph, cx->op->mean_excitation_ev, cx->op->electron_cutoff_mev,
-                                   r, iv, p, te, walk_deposit, &sink);
+                                   r, iv, p, te, walk_deposit, &sink, NULL);
   if (esc > 0.0) {
     loc->ledger[L_ESC] += esc;
     loc->rec[1] += esc;
@@ -1029,6 +1052,108 @@ static void sample_decay(const orc_ctx *cx, orc_stream *st, int64_t iv0[3], doub
   r0[2] = ((double)iv0[2] + stream_uniform(st)) * ph->dz;
 }
 
+/* ------------------------------------------------------------------ */
+/* 18F positrons: kinetic energy, range and the pair's non-collinearity */
+/* ------------------------------------------------------------------ */
+
+/* Allowed beta+ spectrum (Fermi theory of beta decay), unnormalised:
+ * dN/dT = p W (W0 - W)^2 F(W), with W = 1 + T / m_e c^2 the positron's total
+ * energy, p = sqrt(W^2 - 1) its momentum (units of m_e c^2 and m_e c), W0 the
+ * total energy at the endpoint, and F the non-relativistic Fermi function
+ * 2 pi eta / (1 - exp(-2 pi eta)) with eta = -Z_d alpha W / p: the positron
+ * is repelled by the daughter nucleus's charge Z_d. */
+double orc_beta_plus_shape(double t)
+{
+  if (!(t > 0.0) || !(t < ORC_F18_T0)) return 0.0;
+  const double w = 1.0 + t / ORC_MEC2_MEV, w0 = 1.0 + ORC_F18_T0 / ORC_MEC2_MEV;
+  const double p = sqrt(w * w - 1.0);
+  const double x = -2.0 * ORC_PI * ORC_F18_ZD * ORC_ALPHA * w / p; /* 2 pi eta < 0 */
+  const double f = x / -expm1(-x);
+  return p * w * (w0 - w) * (w0 - w) * f;
+}
+
+/* The spectrum's CDF on the nodes T_i = T0 i / ORC_POS_CDF_N, each interval
+ * integrated by 4-point Gauss-Legendre, normalised to 1 at T0. */
+static void build_positron_cdf(double *cdf)
+{
+  static const double x[2] = { 0.3399810435848563, 0.8611363115940526 };
+  static const double w[2] = { 0.6521451548625461, 0.3478548451374538 };
+  const double h = ORC_F18_T0 / ORC_POS_CDF_N;
+  cdf[0] = 0.0;
+  for (int i = 0; i < ORC_POS_CDF_N; ++i) {
+    const double c = (i + 0.5) * h;
+    double acc = 0.0;
+    for (int q = 0; q < 2; ++q)
+      acc += w[q] * (orc_beta_plus_shape(c - 0.5 * h * x[q]) +
+                     orc_beta_plus_shape(c + 0.5 * h * x[q]));
+    cdf[i + 1] = cdf[i] + 0.5 * h * acc;
+  }
+  const double tot = cdf[ORC_POS_CDF_N];
+  for (int i = 1; i <= ORC_POS_CDF_N; ++i) cdf[i] /= tot;
+}
+
+/* Kinetic energy of the positron for the uniform u: the CDF inverted on
+ * its nodes, linearly within an interval. */
+static double positron_energy(const double *cdf, double u)
+{
+  int lo = 0, hi = ORC_POS_CDF_N;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (cdf[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  const double h = ORC_F18_T0 / ORC_POS_CDF_N;
+  const double span = cdf[lo + 1] - cdf[lo];
+  const double f = span > 0.0 ? (u - cdf[lo]) / span : 0.0;
+  return (lo + f) * h;
+}
+
+/* Polar angle of the pair's deviation from back to back: the deviation is
+ * an isotropic two-dimensional Gaussian of the given FWHM, so its size is
+ * Rayleigh distributed, sigma sqrt(-2 ln u). */
+static double noncollinear_angle(double fwhm, double u)
+{
+  const double sigma = fwhm / (2.0 * sqrt(2.0 * log(2.0)));
+  return sigma * sqrt(-2.0 * log(u));
+}
+
+/* The positron of a decay at r0 (voxel iv0): its kinetic energy (one
+ * uniform) and direction (Marsaglia), then its straight CSDA walk down to
+ * ORC_POS_FLOOR, each voxel's loss booked as a positron deposit.  Moves
+ * r0 / iv0 to the annihilation point.  Returns 1 when the positron leaves
+ * the grid (then the pair is born outside it and escapes). */
+static int positron_start(const orc_ctx *cx, orc_stream *st, double r0[3], int64_t iv0[3],
+                          dep_list *l, orc_local *loc)
+{
+  const orc_phantom *ph = cx->ph;
+  const double t = positron_energy(cx->pos_cdf, stream_uniform(st));
+  double dp[3];
+  sample_marsaglia(st, dp);
+  loc->ledger[L_EMIT] += t;
+  const int64_t v0 = iv0[0] + (int64_t)ph->nx * (iv0[1] + (int64_t)ph->ny * iv0[2]);
+  if (!(t > ORC_POS_FLOOR)) { /* too slow to move: it stops where it was born */
+    add_dep(l, loc, v0, t, L_DEP_POS);
+    return 0;
+  }
+  walk_sink sink = { l, loc, L_DEP_POS };
+  double end[3];
+  const double esc = electron_walk(ph, cx->op->mean_excitation_ev, ORC_POS_FLOOR, r0, iv0, dp, t,
+                                   walk_deposit, &sink, end);
+  if (esc > 0.0) {
+    loc->ledger[L_ESC] += esc;
+    loc->rec[1] += esc;
+    return 1;
+  }
+  const double h[3] = { ph->dx, ph->dy, ph->dz };
+  const int32_t n[3] = { ph->nx, ph->ny, ph->nz };
+  for (int a = 0; a < 3; ++a) {
+    r0[a] = end[a];
+    int64_t i = (int64_t)floor(end[a] / h[a]);
+    iv0[a] = i < 0 ? 0 : (i >= n[a] ? n[a] - 1 : i);
+  }
+  return 0;
+}
+
 static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local *loc,
                         const orc_tally *tal)
 {
@@ -1055,17 +1180,30 @@ static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local 
     sample_decay(cx, &st, iv0, r0);
     sample_marsaglia(&st, d0);
   }
+  /* the positron's walk; the pair is born where it ends */
+  const int positron = op->positron && op->source_kind != ORC_SRC_PENCIL;
+  const int pair_outside = positron && positron_start(cx, &st, r0, iv0, l, loc);
   for (int p = 0; p < nph; ++p) {
     double r[3] = { r0[0], r0[1], r0[2] };
     double d[3] = { d0[0], d0[1], d0[2] };
     int64_t iv[3] = { iv0[0], iv0[1], iv0[2] };
+    loc->ledger[L_EMIT] += ORC_E0_MEV;
+    loc->stats[S_PHOTONS]++;
+    if (pair_outside) { /* born outside the grid: escapes, draws nothing */
+      loc->ledger[L_ESC] += ORC_E0_MEV;
+      loc->rec[1] += ORC_E0_MEV;
+      loc->stats[S_ESCAPES]++;
+      continue;
+    }
     if (p == 1) {
       d[0] = -d0[0];
       d[1] = -d0[1];
       d[2] = -d0[2];
+      if (positron) { /* non-collinearity: two uniforms as the photon starts */
+        const double u1 = stream_uniform(&st), u2 = stream_uniform(&st);
+        rotate_dir(d, cos(noncollinear_angle(op->noncol_fwhm_rad, u1)), u2);
+      }
     }
-    loc->ledger[L_EMIT] += ORC_E0_MEV;
-    loc->stats[S_PHOTONS]++;
     if (op->tracking != ORC_TRACK_EXACT)
       photon_woodcock(cx, &st, r, d, l, loc);
     else
@@ -1129,11 +1267,12 @@ int orc_run(const orc_phantom *ph, const orc_opts *op, orc_tally *tal)
     return -1;
   if (op->photons_per_decay < 1 || op->photons_per_decay > 2) return -1;
   if (op->tracking < ORC_TRACK_EXACT || op->tracking > ORC_TRACK_REGIONS) return -1;
-  if (op->electron_cutoff_mev > 0.0) {
+  if (op->electron_cutoff_mev > 0.0 || op->positron) {
     if (!op->mean_excitation_ev) return -1;
     for (int m = 0; m < ph->n_mat; ++m)
       if (!(op->mean_excitation_ev[m] > 0.0)) return -1;
   }
+  if (op->positron && !(op->noncol_fwhm_rad >= 0.0 && op->noncol_fwhm_rad < 0.1)) return -1;
   const int64_t nvox = (int64_t)ph->nx * ph->ny * ph->nz;
   for (int64_t v = 0; v < nvox; ++v) {
     if (ph->material[v] >= ph->n_mat || !(ph->density[v] > 0.0) || isinf(ph->density[v]))
@@ -1178,6 +1317,12 @@ int orc_run(const orc_phantom *ph, const orc_opts *op, orc_tally *tal)
     }
   }
   cx.cdf = cdf;
+  double pos_cdf[ORC_POS_CDF_N + 1];
+  cx.pos_cdf = NULL;
+  if (op->positron) {
+    build_positron_cdf(pos_cdf);
+    cx.pos_cdf = pos_cdf;
+  }
 
   double ledger[ORC_LEDGER_N] = { 0 };
   uint64_t stats[ORC_STATS_N] = { 0 };
@@ -1287,11 +1432,15 @@ void orc_organ_stats(const double *dose_rate, const double *rel_unc, const uint8
 
 /* kind 0: raw Philox words; 1: uniforms; 2: Marsaglia directions (3 per
  * sample); 3: Kahn KN (eps, cos); 4: Butcher-Messel KN (eps, cos);
- * 5: Thomson cos.  Sample i uses the stream of history i. */
+ * 5: Thomson cos; 6: 18F positron kinetic energy (MeV); 7: the pair's
+ * deviation angle from back to back (rad) for a FWHM of e_mev rad.
+ * Sample i uses the stream of history i. */
 int orc_sample(int kind, double e_mev, uint64_t n, uint64_t seed, int wide, int rng,
                double *out)
 {
   const double k = e_mev / ORC_MEC2_MEV;
+  double pos_cdf[ORC_POS_CDF_N + 1];
+  if (kind == 6) build_positron_cdf(pos_cdf);
   for (uint64_t i = 0; i < n; ++i) {
     orc_stream st;
     stream_init(&st, seed, i, 0, wide, rng);
@@ -1313,6 +1462,12 @@ int orc_sample(int kind, double e_mev, uint64_t n, uint64_t seed, int wide, int 
       break;
     case 5:
       out[i] = sample_thomson(stream_uniform(&st));
+      break;
+    case 6:
+      out[i] = positron_energy(pos_cdf, stream_uniform(&st));
+      break;
+    case 7:
+      out[i] = noncollinear_angle(e_mev, stream_uniform(&st));
       break;
     default:
       return -1;
@@ -1432,7 +1587,7 @@ int orc_electron_walk(const orc_phantom *ph, const double *i_ev, double cutoff, 
     walk_collect(&o, iv[0] + (int64_t)n[0] * (iv[1] + (int64_t)n[1] * iv[2]), t0);
     return o.n;
   }
-  *escaped = electron_walk(ph, i_ev, cutoff, r, iv, de, t0, walk_collect, &o);
+  *escaped = electron_walk(ph, i_ev, cutoff, r, iv, de, t0, walk_collect, &o, NULL);
   return o.n;
 }
 

@@ -37,5 +37,5 @@ def oracle_phantom(orc, prob, activity=True):
 
 
 def ledger_balance(led):
-    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"]
+    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"] + led.get("dep_positron", 0.0)
     return (dep + led["escaped"] + led["discarded"]) / led["emitted"] - 1.0

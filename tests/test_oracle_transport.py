@@ -30,7 +30,7 @@ def _mu(orc, z, zoa, rho, e=0.511):
 
 
 def _balance(led):
-    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"]
+    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"] + led.get("dep_positron", 0.0)
     return (dep + led["escaped"] + led["discarded"]) / led["emitted"] - 1.0
 
 
