@@ -1118,17 +1118,20 @@ static double noncollinear_angle(double fwhm, double u)
 }
 
 /* The positron of a decay at r0 (voxel iv0): its kinetic energy (one
- * uniform) and direction (Marsaglia), then its straight CSDA walk down to
+ * uniform), its direction (Marsaglia) and the two uniforms of the pair's
+ * deviation from back to back (*u_dev), then its straight CSDA walk down to
  * ORC_POS_FLOOR, each voxel's loss booked as a positron deposit.  Moves
  * r0 / iv0 to the annihilation point.  Returns 1 when the positron leaves
  * the grid (then the pair is born outside it and escapes). */
 static int positron_start(const orc_ctx *cx, orc_stream *st, double r0[3], int64_t iv0[3],
-                          dep_list *l, orc_local *loc)
+                          double u_dev[2], dep_list *l, orc_local *loc)
 {
   const orc_phantom *ph = cx->ph;
   const double t = positron_energy(cx->pos_cdf, stream_uniform(st));
   double dp[3];
   sample_marsaglia(st, dp);
+  u_dev[0] = stream_uniform(st);
+  u_dev[1] = stream_uniform(st);
   loc->ledger[L_EMIT] += t;
   const int64_t v0 = iv0[0] + (int64_t)ph->nx * (iv0[1] + (int64_t)ph->ny * iv0[2]);
   if (!(t > ORC_POS_FLOOR)) { /* too slow to move: it stops where it was born */
@@ -1182,7 +1185,8 @@ static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local 
   }
   /* the positron's walk; the pair is born where it ends */
   const int positron = op->positron && op->source_kind != ORC_SRC_PENCIL;
-  const int pair_outside = positron && positron_start(cx, &st, r0, iv0, l, loc);
+  double u_dev[2] = { 0.5, 0.5 };
+  const int pair_outside = positron && positron_start(cx, &st, r0, iv0, u_dev, l, loc);
   for (int p = 0; p < nph; ++p) {
     double r[3] = { r0[0], r0[1], r0[2] };
     double d[3] = { d0[0], d0[1], d0[2] };
@@ -1199,10 +1203,8 @@ static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local 
       d[0] = -d0[0];
       d[1] = -d0[1];
       d[2] = -d0[2];
-      if (positron) { /* non-collinearity: two uniforms as the photon starts */
-        const double u1 = stream_uniform(&st), u2 = stream_uniform(&st);
-        rotate_dir(d, cos(noncollinear_angle(op->noncol_fwhm_rad, u1)), u2);
-      }
+      if (positron) /* non-collinearity, from the uniforms drawn with the positron */
+        rotate_dir(d, cos(noncollinear_angle(op->noncol_fwhm_rad, u_dev[0])), u_dev[1]);
     }
     if (op->tracking != ORC_TRACK_EXACT)
       photon_woodcock(cx, &st, r, d, l, loc);
