@@ -167,6 +167,9 @@ def main():
     ap.add_argument("--electrons", type=float, default=0.0, metavar="MEV",
                     help="plain MC workloads: walk Compton electrons above this cutoff "
                          "(Section 2.1 uses 0.2 MeV); 0 deposits them on the spot")
+    ap.add_argument("--positrons", action="store_true",
+                    help="plain MC workloads: 18F positron range and the pair's "
+                         "non-collinearity (FWHM 0.5 degrees)")
     ap.add_argument("--tracking", choices=("global", "regions"), default="global",
                     help="plain MC and batch64 workloads: Woodcock majorant for the whole "
                          "phantom (global) or by region (the box of the dense voxels, and "
@@ -249,10 +252,13 @@ def bench_mc(args):
     if args.tracking != "global":
         B.nmd_set_tracking(eng.ctx, 0, args.tracking)
         what += "; Woodcock majorants by region"
+    iev = [P.MEAN_EXCITATION_EV[next(k for k in P.MATERIALS
+                                     if tuple(P.MATERIALS[k][:2]) == tuple(m))]
+           for m in prob.materials]
+    if args.positrons:
+        B.nmd_set_positron(eng.ctx, 0, True, 0.5, iev)
+        what += "; 18F positrons walked (CSDA), pair non-collinearity 0.5 deg FWHM"
     if args.electrons > 0:
-        iev = [P.MEAN_EXCITATION_EV[next(k for k in P.MATERIALS
-                                         if tuple(P.MATERIALS[k][:2]) == tuple(m))]
-               for m in prob.materials]
         B.nmd_set_electrons(eng.ctx, 0, args.electrons, iev)
         what += "; Compton electrons above %g MeV walked (CSDA, straight ahead)" % args.electrons
     opts = B.nmd_run_opts_default()
@@ -288,7 +294,7 @@ def bench_mc(args):
     led = eng.ledger(0)
     total = args.steps * nd
     value = total / dt
-    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"]
+    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"] + led["dep_positron"]
     balance = (dep + led["escaped"] + led["discarded"]) / led["emitted"] - 1.0
     print(json.dumps({"steps_ms": [round(a.elapsed_time(b), 3) for a, b in evs],
                       "stats_per_decay": {k: v / total for k, v in stats.items()},
@@ -313,9 +319,11 @@ def bench_mc(args):
         "config": {"workload": what, "decays_per_step": nd, "decays_per_job": total,
                    "photons_per_decay": prob.photons_per_decay,
                    "electron_cutoff_mev": args.electrons or None,
-                   "tracking": args.tracking, "tally": "f64", "transport": "f32"},
+                   "tracking": args.tracking, "positrons": args.positrons,
+                   "tally": "f64", "transport": "f32"},
         "roofline": transport_roofline(per_decay, nd, kern_ms,
-                                       None if args.electrons or args.tracking != "global"
+                                       None if args.electrons or args.positrons or
+                                       args.tracking != "global"
                                        else TRAFFIC_BYTES_PER_DECAY.get(args.workload),
                                        ceilings),
     }

@@ -93,9 +93,11 @@ typedef struct {
  * them as approximate.  NMD_STAT_GATHERS counts the voxel records the flight
  * steps read: at least one per step inside the grid, plus the records read
  * ahead for a second step that a real collision or an escape then made
- * unnecessary. */
+ * unnecessary.  With positrons on (nmd_set_positron), NMD_LEDGER_EMITTED
+ * holds the photons' energy plus the positrons' kinetic energy, and
+ * NMD_LEDGER_DEP_POSITRON what the positrons lost in the grid. */
 enum { NMD_LEDGER_EMITTED = 0, NMD_LEDGER_DEP_COMPTON, NMD_LEDGER_DEP_PE, NMD_LEDGER_DEP_CUTOFF,
-       NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_N };
+       NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_DEP_POSITRON, NMD_LEDGER_N };
 enum { NMD_STAT_HISTORIES = 0, NMD_STAT_PHOTONS, NMD_STAT_STEPS, NMD_STAT_NULLS,
        NMD_STAT_COMPTON, NMD_STAT_PE, NMD_STAT_RAYLEIGH, NMD_STAT_DEPOSITS, NMD_STAT_MERGED,
        NMD_STAT_MAX_MERGED, NMD_STAT_ESCAPES, NMD_STAT_OVERFLOWS, NMD_STAT_CLAIMS,
@@ -161,6 +163,36 @@ nmd_status nmd_set_activity(nmd_ctx *ctx, int32_t phantom_id, const float *activ
  * it.  Synchronises the stream. */
 nmd_status nmd_set_electrons(nmd_ctx *ctx, int32_t phantom_id, double cutoff_mev,
                              const double *mean_excitation_ev);
+
+/* Positron physics of 18F (the emitter of Section 2.1; the paper leaves its
+ * positron out).  With on = 1 every decay of the activity source emits a
+ * positron before its photon pair:
+ *   - its kinetic energy from the allowed beta+ spectrum of 18F (Fermi
+ *     theory: p W (W0 - W)^2 F(W) in units of the electron's rest energy,
+ *     endpoint 633.5 keV, F the non-relativistic Fermi function of a
+ *     positron repelled by the 18O nucleus), tabulated by the library;
+ *   - an isotropic direction, along which it slows down continuously on a
+ *     straight line as the electrons of nmd_set_electrons do (Bethe stopping
+ *     power of its material, mean excitation energies mean_excitation_ev),
+ *     down to 1 keV; its losses are booked as NMD_LEDGER_DEP_POSITRON and
+ *     its kinetic energy as emitted;
+ *   - the photon pair is born where it stops; one that leaves the grid
+ *     takes the pair with it (both photons escape);
+ *   - the second photon leaves back to back with the first, tilted by an
+ *     angle whose size is Rayleigh distributed with FWHM noncol_fwhm_deg
+ *     (in [0, 5] degrees; 0 keeps the pair exactly back to back) about an
+ *     isotropic azimuth.
+ * Per decay the draws are: the decay voxel and position, the pair's
+ * direction, then one uniform for the kinetic energy, the positron's
+ * direction and two uniforms for the tilt.  Pencil-beam runs emit no
+ * positron.  on = 0 turns it off (mean_excitation_ev may then be NULL).
+ * Independent of nmd_set_electrons: the positron tables run from 1 keV to
+ * 640 keV.  Resets the phantom's tallies; re-registering the phantom drops
+ * it; checkpoints do not record it; graphs captured before the call refuse
+ * to launch.  Errors: NMD_E_STATE (phantom not registered), NMD_E_INVALID
+ * (arguments).  Synchronises the stream. */
+nmd_status nmd_set_positron(nmd_ctx *ctx, int32_t phantom_id, int32_t on, double noncol_fwhm_deg,
+                            const double *mean_excitation_ev);
 
 /* Woodcock tracking modes (the free flight of Section 2.1 samples collision
  * points against a majorant of the attenuation, with null collisions making

@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnmdose.so")
 
-LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded")
+LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded",
+                 "dep_positron")
 STATS_FIELDS = ("histories", "photons", "steps", "nulls", "compton", "photoelectric",
                 "rayleigh", "deposits", "merged", "max_merged", "escapes", "overflows",
                 "claims", "rng_blocks", "list_merges", "gathers")
@@ -82,8 +83,8 @@ EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
            "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
            "nmd_graph_launch", "nmd_graph_destroy", "nmd_save", "nmd_load",
-           "nmd_set_electrons", "nmd_set_tracking") + NN_EXPORTS + INGEST_EXPORTS + \
-    PROBE_EXPORTS
+           "nmd_set_electrons", "nmd_set_tracking", "nmd_set_positron") + NN_EXPORTS + \
+    INGEST_EXPORTS + PROBE_EXPORTS
 
 _lib = None
 
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH):
         "nmd_save": [vp, i32, ctypes.c_char_p],
         "nmd_set_electrons": [vp, i32, d, vp],
         "nmd_set_tracking": [vp, i32, i32],
+        "nmd_set_positron": [vp, i32, i32, d, vp],
         "nmd_load": [vp, i32, ctypes.c_char_p],
         "nmd_graph_destroy": [vp],
         "nmd_conv3d_fwd": [vp, i32, i32, i32, i32, ctypes.POINTER(nmd_nn_src), vp, vp, i32, i32,
@@ -280,6 +282,17 @@ def nmd_set_electrons(ctx, phantom_id, cutoff_mev, mean_excitation_ev=None):
         arr = np.ascontiguousarray(mean_excitation_ev, dtype=np.float64)
     _check(ctx, load_library().nmd_set_electrons(
         ctx, int(phantom_id), float(cutoff_mev),
+        None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)))
+
+
+def nmd_set_positron(ctx, phantom_id, on, noncol_fwhm_deg=0.5, mean_excitation_ev=None):
+    """on: 18F positron range and the pair's non-collinearity (one mean
+    excitation energy in eV per material of the phantom); off: none."""
+    arr = None
+    if mean_excitation_ev is not None:
+        arr = np.ascontiguousarray(mean_excitation_ev, dtype=np.float64)
+    _check(ctx, load_library().nmd_set_positron(
+        ctx, int(phantom_id), int(bool(on)), float(noncol_fwhm_deg),
         None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)))
 
 

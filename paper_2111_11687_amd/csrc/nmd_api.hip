@@ -76,6 +76,9 @@ struct Phantom {
   int n_mat = 0;
   std::vector<double> mat_zoa;  // Z/A of each material
   DevBuf e_tab, e_inv_dr, e_slot;  // electron range tables (nmd_set_electrons)
+  DevBuf p_cdf, p_guide, p_tab, p_inv_dr, p_slot;  // positron tables (nmd_set_positron)
+  int32_t p_on = 0;
+  float p_inv_dt = 0.0f, noncol_sigma = 0.0f;
   int32_t box0[3] = {0, 0, 0}, box1[3] = {0, 0, 0};  // inner box, voxel indices [box0, box1)
   double out_ratio = 0.0;  // outer majorant / inner majorant (0: no outer region)
   int32_t tracking = NMD_TRACK_GLOBAL;  // NMD_TRACK_* (nmd_set_tracking)
@@ -189,13 +192,13 @@ double electron_stopping(double t, double zoa, double i_ev) {
 constexpr double kETabTop = 0.345;  // MeV, above the largest Compton electron of 0.511 MeV
 
 // Range above the cutoff, R(T) = integral_cut^T dT' / S(T') (g/cm^2), on the
-// kETab nodes T_i = cut + i dt, and its inverse T(R) on R_j = j dr, for one
-// material; the integral by 3-point Gauss-Legendre on 16 sub-intervals of
-// every node interval.
-void electron_tables(double cut, double zoa, double i_ev, float *r_tab, float *t_tab,
-                     float *inv_dr) {
+// kETab nodes T_i = cut + i dt up to top, and its inverse T(R) on
+// R_j = j dr, for one material; the integral by 3-point Gauss-Legendre on 16
+// sub-intervals of every node interval.
+void electron_tables(double cut, double top, double zoa, double i_ev, float *r_tab,
+                     float *t_tab, float *inv_dr) {
   const int sub = 16, nf = (kETab - 1) * sub;
-  const double dt = (kETabTop - cut) / (kETab - 1), h = dt / sub;
+  const double dt = (top - cut) / (kETab - 1), h = dt / sub;
   const double xg[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)}, wg[3] = {5.0 / 9, 8.0 / 9, 5.0 / 9};
   std::vector<double> rf(nf + 1, 0.0);
   for (int k = 0; k < nf; ++k) {
@@ -214,6 +217,49 @@ void electron_tables(double cut, double zoa, double i_ev, float *r_tab, float *t
     t_tab[j] = (float)(cut + (k + std::min(std::max(f, 0.0), 1.0)) * h);
   }
   *inv_dr = (float)(1.0 / dr);
+}
+
+// ---- 18F positrons (host) ---------------------------------------------------
+constexpr double kF18DaughterZ = 8.0;    // 18O
+constexpr double kAlpha = 1.0 / 137.035999084;
+
+// Allowed beta+ spectrum dN/dT (unnormalised): p W (W0 - W)^2 F with W the
+// total energy over m_e c^2, p the momentum over m_e c and F the
+// non-relativistic Fermi function 2 pi eta / (1 - exp(-2 pi eta)),
+// eta = -Z alpha W / p for a positron and a daughter of charge Z.
+double beta_plus_density(double t) {
+  if (!(t > 0.0) || !(t < kF18T0)) return 0.0;
+  const double w = 1.0 + t / kMeC2, w0 = 1.0 + kF18T0 / kMeC2;
+  const double p = std::sqrt(w * w - 1.0);
+  const double y = 2.0 * M_PI * kF18DaughterZ * kAlpha * w / p;  // -2 pi eta > 0
+  return p * w * (w0 - w) * (w0 - w) * (y / std::expm1(y));
+}
+
+// The spectrum's CDF on T_i = T0 i / kPosN (3-point Gauss-Legendre on 8
+// sub-intervals of each interval), normalised to 1 at T0, and its guide
+// table: guide[k] = the last i with cdf[i] <= k / kPosN (Chen and Asau), so
+// that a uniform u finds its interval from guide[floor(u kPosN)] in a step
+// or two.
+void positron_cdf(double *cdf, int32_t *guide) {
+  const int sub = 8;
+  const double h = kF18T0 / kPosN, hs = h / sub;
+  const double xg[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)}, wg[3] = {5.0 / 9, 8.0 / 9, 5.0 / 9};
+  cdf[0] = 0.0;
+  for (int i = 0; i < kPosN; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < sub; ++k) {
+      const double c = i * h + (k + 0.5) * hs;
+      for (int q = 0; q < 3; ++q) acc += wg[q] * beta_plus_density(c + 0.5 * hs * xg[q]);
+    }
+    cdf[i + 1] = cdf[i] + 0.5 * hs * acc;
+  }
+  for (int i = 1; i <= kPosN; ++i) cdf[i] /= cdf[kPosN];
+  int i = 0;
+  for (int k = 0; k < kPosN; ++k) {
+    const double u = (double)k / kPosN;
+    while (i < kPosN - 1 && cdf[i + 1] <= u) ++i;
+    guide[k] = i;
+  }
 }
 
 float round_up_f32(double x) {
@@ -292,6 +338,14 @@ PhantomDesc make_desc(int32_t id, const Phantom &p) {
   d.e_slot = p.e_slot.as<uint8_t>();
   d.e_cut = p.e_cut;
   d.e_inv_dt = p.e_inv_dt;
+  d.p_on = p.p_on;
+  d.p_inv_dt = p.p_inv_dt;
+  d.noncol_sigma = p.noncol_sigma;
+  d.p_cdf = p.p_cdf.as<double>();
+  d.p_guide = p.p_guide.as<int32_t>();
+  d.p_tab = p.p_tab.as<float>();
+  d.p_inv_dr = p.p_inv_dr.as<float>();
+  d.p_slot = p.p_slot.as<uint8_t>();
   return d;
 }
 
@@ -437,7 +491,7 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
   for (int32_t i : ids) n_slots = std::max(n_slots, c->ph[i].n_org + 1);
   pl.debug = o.history_records != nullptr;
   pl.electrons = false;
-  for (int32_t i : ids) pl.electrons = pl.electrons || c->ph[i].e_cut > 0.0f;
+  for (int32_t i : ids) pl.electrons = pl.electrons || c->ph[i].e_cut > 0.0f || c->ph[i].p_on;
   pl.regions = false;
   for (int32_t i : ids)
     pl.regions = pl.regions ||
@@ -1032,8 +1086,8 @@ nmd_status nmd_set_electrons(nmd_ctx *c, int32_t id, double cutoff_mev,
     const float cut = (float)cutoff_mev;
     std::vector<float> tab((size_t)kMaxMaterials * 2 * kETab, 0.0f), inv_dr(kMaxMaterials, 0.0f);
     for (int m = 0; m < p->n_mat; ++m)
-      electron_tables((double)cut, p->mat_zoa[m], mean_excitation_ev[m], &tab[(size_t)m * 2 * kETab],
-                      &tab[(size_t)m * 2 * kETab + kETab], &inv_dr[m]);
+      electron_tables((double)cut, kETabTop, p->mat_zoa[m], mean_excitation_ev[m],
+                      &tab[(size_t)m * 2 * kETab], &tab[(size_t)m * 2 * kETab + kETab], &inv_dr[m]);
     std::vector<uint8_t> slot(kMaxPalette, 0);
     for (int q = 0; q < kMaxPalette; ++q) slot[q] = (uint8_t)std::max(p->pal_mat[q], 0);
     DevBuf dt, dr, ds;
@@ -1050,6 +1104,68 @@ nmd_status nmd_set_electrons(nmd_ctx *c, int32_t id, double cutoff_mev,
     p->e_slot = std::move(ds);
     p->e_cut = cut;
     p->e_inv_dt = (float)((kETab - 1) / (kETabTop - (double)cut));
+  }
+  p->gen = c->next_gen++;
+  if (p->has_activity && (s = zero_tallies(c, *p))) return s;
+  return upload_desc(c, id, *p);
+}
+
+nmd_status nmd_set_positron(nmd_ctx *c, int32_t id, int32_t on, double noncol_fwhm_deg,
+                            const double *mean_excitation_ev) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (on != 0 && on != 1) return fail(c, NMD_E_INVALID, "on must be 0 or 1");
+  if (!on) {
+    p->p_cdf.release();
+    p->p_guide.release();
+    p->p_tab.release();
+    p->p_inv_dr.release();
+    p->p_slot.release();
+    p->p_on = 0;
+    p->p_inv_dt = 0.0f;
+    p->noncol_sigma = 0.0f;
+  } else {
+    if (!(noncol_fwhm_deg >= 0.0 && noncol_fwhm_deg <= 5.0))
+      return fail(c, NMD_E_INVALID, "non-collinearity FWHM must lie in [0, 5] degrees");
+    if (!mean_excitation_ev)
+      return fail(c, NMD_E_INVALID, "mean excitation energies are required");
+    for (int m = 0; m < p->n_mat; ++m)
+      if (!(mean_excitation_ev[m] > 1.0 && mean_excitation_ev[m] < 1.0e4))
+        return fail(c, NMD_E_INVALID, "mean excitation energy of material %d must lie in "
+                    "(1, 10^4) eV", m);
+    std::vector<float> tab((size_t)kMaxMaterials * 2 * kETab, 0.0f), inv_dr(kMaxMaterials, 0.0f);
+    for (int m = 0; m < p->n_mat; ++m)
+      electron_tables((double)kPosFloor, kPosTop, p->mat_zoa[m], mean_excitation_ev[m],
+                      &tab[(size_t)m * 2 * kETab], &tab[(size_t)m * 2 * kETab + kETab], &inv_dr[m]);
+    std::vector<double> cdf(kPosN + 1);
+    std::vector<int32_t> guide(kPosN);
+    positron_cdf(cdf.data(), guide.data());
+    std::vector<uint8_t> slot(kMaxPalette, 0);
+    for (int q = 0; q < kMaxPalette; ++q) slot[q] = (uint8_t)std::max(p->pal_mat[q], 0);
+    DevBuf dc, dg, dt, dr, ds;
+    if ((s = dev_alloc(c, dc, cdf.size() * sizeof(double))) ||
+        (s = dev_alloc(c, dg, guide.size() * sizeof(int32_t))) ||
+        (s = dev_alloc(c, dt, tab.size() * sizeof(float))) ||
+        (s = dev_alloc(c, dr, inv_dr.size() * sizeof(float))) ||
+        (s = dev_alloc(c, ds, slot.size())))
+      return s;
+    HIP_TRY(c, hipMemcpyAsync(dc.p, cdf.data(), dc.n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dg.p, guide.data(), dg.n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dt.p, tab.data(), dt.n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dr.p, inv_dr.data(), dr.n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(ds.p, slot.data(), ds.n, hipMemcpyHostToDevice, c->stream));
+    if ((s = sync(c))) return s;
+    p->p_cdf = std::move(dc);
+    p->p_guide = std::move(dg);
+    p->p_tab = std::move(dt);
+    p->p_inv_dr = std::move(dr);
+    p->p_slot = std::move(ds);
+    p->p_on = 1;
+    p->p_inv_dt = (float)((kETab - 1) / (kPosTop - (double)kPosFloor));
+    // Rayleigh scale sigma = FWHM / (2 sqrt(2 ln 2)) of the tilt's size
+    p->noncol_sigma = (float)(noncol_fwhm_deg * M_PI / 180.0 / (2.0 * std::sqrt(2.0 * M_LN2)));
   }
   p->gen = c->next_gen++;
   if (p->has_activity && (s = zero_tallies(c, *p))) return s;
@@ -1295,7 +1411,8 @@ nmd_status nmd_get_ledger(nmd_ctx *c, int32_t id, double *ledger) {
   HIP_TRY(c, hipMemcpyAsync(l, p->ledger.p, sizeof l, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(st, p->stats.p, sizeof st, hipMemcpyDeviceToHost, c->stream));
   if ((s = sync(c))) return s;
-  ledger[0] = (double)st[NMD_STAT_PHOTONS] * (double)kE0;
+  // the photons' energy, and the positrons' kinetic energy counted on the device
+  ledger[0] = (double)st[NMD_STAT_PHOTONS] * (double)kE0 + l[0];
   for (int i = 1; i < NMD_LEDGER_N; ++i) ledger[i] = l[i];
   return NMD_OK;
 }

@@ -196,11 +196,12 @@ __device__ __forceinline__ float thomson(float u) {
   return copysignf(w - 1.0f / w, a);
 }
 
-// Rotate (ux,uy,uz) by polar cos(theta) and azimuth 2 pi uphi about the
-// orthonormal basis of Duff et al. (JCGT 2017): no pole special case and no
-// loss of precision near the z axis in FP32.
-__device__ __forceinline__ void rotate(float &ux, float &uy, float &uz, float cost, float uphi) {
-  const float sint = __builtin_sqrtf(fmaxf(0.0f, 1.0f - cost * cost));
+// Rotate (ux,uy,uz) by the polar angle theta (its cosine and sine given) and
+// the azimuth 2 pi uphi about the orthonormal basis of Duff et al. (JCGT
+// 2017): no pole special case and no loss of precision near the z axis in
+// FP32.
+__device__ __forceinline__ void rotate_sc(float &ux, float &uy, float &uz, float cost, float sint,
+                                          float uphi) {
   const float cphi = __builtin_amdgcn_cosf(uphi);  // argument in revolutions
   const float sphi = __builtin_amdgcn_sinf(uphi);
   const float sg = uz >= 0.0f ? 1.0f : -1.0f;
@@ -214,6 +215,12 @@ __device__ __forceinline__ void rotate(float &ux, float &uy, float &uz, float co
   ux = nu * n;
   uy = nv * n;
   uz = nw * n;
+}
+
+// The same with sin(theta) = sqrt(1 - cos^2(theta)), for angles that are not
+// small (small ones lose their digits there and pass the sine instead).
+__device__ __forceinline__ void rotate(float &ux, float &uy, float &uz, float cost, float uphi) {
+  rotate_sc(ux, uy, uz, cost, __builtin_sqrtf(fmaxf(0.0f, 1.0f - cost * cost)), uphi);
 }
 
 // Energy-dependent factors: mu_C = cC * sig, mu_PE = cPE * gpe, mu_R = cR * gr

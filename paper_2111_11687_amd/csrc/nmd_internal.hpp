@@ -28,6 +28,10 @@ constexpr uint32_t kMaxPhotonSteps = 1u << 20;  // termination bound per photon
 constexpr int kETab = 256;                // nodes of the electron range and inverse-range tables
 constexpr int kMaxMaterials = 8;
 constexpr float kInnerRho = 0.01f;        // g/cm^3: voxels at least this dense lie in the inner box
+constexpr int kPosN = 4096;               // energy intervals of the positron spectrum's CDF
+constexpr double kF18T0 = 0.6335;         // MeV, 18F beta+ endpoint kinetic energy
+constexpr float kPosFloor = 0.001f;       // MeV: a positron stops when its range above this runs out
+constexpr double kPosTop = 0.64;          // MeV: top of the positron range tables (endpoint 0.6335)
 
 // Workgroups of the transport kernel the compiler must fit on one CU (it
 // caps registers accordingly); a build-time tuning knob.
@@ -81,6 +85,18 @@ struct PhantomDesc {
   const uint8_t *e_slot; // [kMaxPalette]: palette index -> material slot
   float e_cut;
   float e_inv_dt;
+  // 18F positrons (p_on): the kinetic-energy CDF on T_i = kF18T0 i / kPosN
+  // and its guide table (p_guide[k] = the last i with p_cdf[i] <= k / kPosN);
+  // range tables as e_tab from kPosFloor on the nodes kPosFloor + i /
+  // p_inv_dt; the Rayleigh scale of the pair's tilt (rad, 0: back to back)
+  int32_t p_on;
+  float p_inv_dt;
+  float noncol_sigma;
+  const double *p_cdf;     // [kPosN + 1]
+  const int32_t *p_guide;  // [kPosN]
+  const float *p_tab;    // [kMaxMaterials][2][kETab]
+  const float *p_inv_dr; // [kMaxMaterials]
+  const uint8_t *p_slot; // [kMaxPalette]: palette index -> material slot
 };
 
 // Per-run fields of one phantom of a launch.

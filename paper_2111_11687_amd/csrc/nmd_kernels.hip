@@ -69,10 +69,10 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
 
 // Per-wave accumulators in LDS, flushed to the phantom's globals when the
 // wave changes phantom or exits.  Ledger slots follow NMD_LEDGER_* (slot 0,
-// emitted, is derived from the photon count on the host); counters follow
-// NMD_STAT_*.
+// emitted, holds the positrons' kinetic energy; the host adds the photons'
+// from their count); counters follow NMD_STAT_*.
 struct WaveAcc {
-  double ledger[6];
+  double ledger[NMD_LEDGER_N];
   unsigned long long stat[kStatN];
   float ep0[5];  // energy_params at the emission energy, for the wave's phantom
 };
@@ -111,7 +111,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <bool kDebug, bool kElectrons, bool kRegions>
-__global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_kernel(RunParams P) {
+__global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) void transport_kernel(RunParams P) {
   __shared__ float4 s_pal[kMaxPalette];
   __shared__ double s_irho[kMaxPalette];  // 1 / density, for the organ scores
   __shared__ float s_kn[kNGrid];
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     s_irho[i] = 1.0 / (double)q.w;
   }
   for (int i = tid; i < kNGrid; i += kBlock) s_kn[i] = P.ln2_kn[i];
-  if (lane < 6) wa.ledger[lane] = 0.0;
+  if (lane < NMD_LEDGER_N) wa.ledger[lane] = 0.0;
   if (lane < kStatN) wa.stat[lane] = 0ull;
   __syncthreads();
 
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   auto flush_wave = [&]() {
     if (wp < 0) return;
     CDesc *d = D;
-    if (lane >= 1 && lane < 6) {
+    if (lane < NMD_LEDGER_N) {
       const double x = wa.ledger[lane];
       if (x != 0.0) gadd(&d->ledger[lane], x);
       wa.ledger[lane] = 0.0;
@@ -377,6 +377,30 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     cnt = 0;
     h_steps = h_nulls = h_cr = h_pe_esc = 0;
     if (kDebug) h_esc = h_disc = 0.0;
+    if (kElectrons && D->p_on && P.source_kind != 1) {
+      // the positron: kinetic energy by inverting the spectrum's CDF
+      // (piecewise linear on kPosN intervals; the guide table gives the
+      // interval's neighbourhood), then its direction; its walk, and the
+      // pair's birth where it ends, wait for an interaction pass (event 4),
+      // as the walks of Compton electrons do
+      const float u = st.uniform();
+      const double ud = (double)u;
+      int k = (int)(u * (float)kPosN);
+      k = k > kPosN - 1 ? kPosN - 1 : k;
+      int i = G(D->p_guide)[k];
+      const double *cdf = D->p_cdf;
+      while (i < kPosN - 1 && G(cdf)[i + 1] <= ud) ++i;
+      const double c0 = G(cdf)[i], c1 = G(cdf)[i + 1];
+      const double f = c1 > c0 ? (ud - c0) / (c1 - c0) : 0.0;
+      E = (float)(((double)i + f) * (kF18T0 / kPosN));  // the positron's kinetic energy
+      marsaglia(st, ux, uy, uz);
+      px = o0;
+      py = o1;
+      pz = o2;
+      ev_t = 4;
+      state = kInteract;
+      return;
+    }
     start_photon();
     state = kFlight;
   };
@@ -652,10 +676,16 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
   // voxel it loses what the voxel's mass path takes off its range above the
   // cutoff; where that range runs out it leaves all it still has.  Each loss
   // goes to the history's deposit list; returns the energy carried out of
-  // the grid.
-  auto electron_walk = [&](float qx, float qy, float qz, double t0) -> double {
+  // the grid.  With is_pos, the particle is the decay's positron, walked from
+  // the decay point with the positron tables down to kPosFloor; (ex, ey, ez)
+  // then receives the point where its range runs out.
+  auto electron_walk = [&](float qx, float qy, float qz, double t0, bool is_pos, float &ex,
+                           float &ey, float &ez) -> double {
     CDesc *d = D;
     const float qq = qx * qx + qy * qy + qz * qz;
+    ex = px;
+    ey = py;
+    ez = pz;
     if (!(qq > 0.0f)) {  // no recoil direction: the energy stays at the event
       atomicAdd(&wa.stat[7], 1ull);
       deposit(ev_v, ev_r, t0);
@@ -669,8 +699,11 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
     const float pos[3] = {px, py, pz};
     const float qv[3] = {qx, qy, qz};
     const int32_t n[3] = {d->nx, d->ny, d->nz};
-    // the event voxel, as the flight step found it
+    // the event voxel, as the flight step found it (a decay point may round
+    // onto the grid's upper face: kept in its voxel)
     int iv[3] = {(int)(px * d->inv_dx), (int)(py * d->inv_dy), (int)(pz * d->inv_dz)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) iv[a] = iv[a] < 0 ? 0 : (iv[a] >= n[a] ? n[a] - 1 : iv[a]);
     float tn[3], td[3];
     int sp[3];
 #pragma unroll
@@ -690,7 +723,11 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       }
       tn[a] = fmaxf(tn[a], 0.0f);
     }
-    const float cut = d->e_cut, inv_dt = d->e_inv_dt;
+    const float cut = is_pos ? kPosFloor : d->e_cut;
+    const float inv_dt = is_pos ? d->p_inv_dt : d->e_inv_dt;
+    const float *tabs = is_pos ? d->p_tab : d->e_tab;
+    const float *inv_drs = is_pos ? d->p_inv_dr : d->e_inv_dr;
+    const uint8_t *slots = is_pos ? d->p_slot : d->e_slot;
     double t = t0;
     float tf = (float)t0;
     float s_cur = 0.0f;
@@ -700,8 +737,8 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       const uint32_t r16 = G(d->rec)[v];
       const uint32_t pq = r16 & 0xFFu;
       const float rho = s_pal[pq].w;
-      const uint32_t slot = G(d->e_slot)[pq];
-      const float *tab = d->e_tab + slot * (2 * kETab);
+      const uint32_t slot = G(slots)[pq];
+      const float *tab = tabs + slot * (2 * kETab);
       int ax = 0;  // ties go to the lower axis
       if (tn[1] < tn[ax]) ax = 1;
       if (tn[2] < tn[ax]) ax = 2;
@@ -717,7 +754,7 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       // energy after the voxel (the cutoff's share stays with the last one)
       float t1 = 0.0f;
       if (!stop) {
-        const float w = (range - mass) * G(d->e_inv_dr)[slot];
+        const float w = (range - mass) * G(inv_drs)[slot];
         int j = (int)w;
         j = j < 0 ? 0 : (j > kETab - 2 ? kETab - 2 : j);
         const float e0 = G(tab)[kETab + j], e1 = G(tab)[kETab + j + 1];
@@ -725,7 +762,13 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
       }
       atomicAdd(&wa.stat[7], 1ull);
       deposit(v, r16, t - (double)t1);  // one call site: one inlined copy
-      if (stop) return 0.0;
+      if (stop) {
+        const float dist = s_cur + fmaxf(range, 0.0f) / rho;
+        ex = pos[0] + dist * qx;
+        ey = pos[1] + dist * qy;
+        ez = pos[2] + dist * qz;
+        return 0.0;
+      }
       t = (double)t1;
       tf = t1;
       s_cur = tnext;
@@ -826,10 +869,15 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
         // next interaction pass, so no lane holds the wave through retries
         float eps = 1.0f, cost = 1.0f;
         if (ev_t != 1 || klein_nishina_try(st, E * (float)(1.0 / kMeC2), eps, cost)) {
-          ++n_real;
+          if (!kElectrons || ev_t != 4) ++n_real;
           ek = (uint32_t)ev_t;
           bool pdone = false;
           double dep = -1.0;  // energy left in voxel ev_v by this event
+          // a walk of this event (one call site, so one inlined copy): 1 the
+          // Compton electron, 2 the decay's positron; its direction and energy
+          uint32_t walk = 0u;
+          float wq0 = 0.0f, wq1 = 0.0f, wq2 = 0.0f;
+          double wt = 0.0;
           if (ev_t == 1) {
             if (kDebug) ++h_cr;
             const float uphi = st.uniform();
@@ -841,13 +889,11 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
                 // the electron is tracked from the event point
                 const float dx0 = ux, dy0 = uy, dz0 = uz;
                 rotate(ux, uy, uz, cost, uphi);
-                const double out = electron_walk(E * dx0 - e1 * ux, E * dy0 - e1 * uy,
-                                                 E * dz0 - e1 * uz, dep);
-                atomicAdd(&wa.ledger[1], dep - out);
-                if (out > 0.0) {
-                  atomicAdd(&wa.ledger[4], out);
-                  if (kDebug) h_esc += out;
-                }
+                wq0 = E * dx0 - e1 * ux;
+                wq1 = E * dy0 - e1 * uy;
+                wq2 = E * dz0 - e1 * uz;
+                wt = dep;
+                walk = 1u;
                 walked = true;
               }
             }
@@ -876,11 +922,70 @@ __global__ __launch_bounds__(kBlock, NMD_TRANSPORT_MIN_BLOCKS) void transport_ke
             dep = (double)E;
             atomicAdd(&wa.ledger[2], dep);
             pdone = true;
+          } else if (kElectrons && ev_t == 4) {
+            // the decay's positron, from the decay point (px, py, pz) along
+            // (ux, uy, uz) with kinetic energy E
+            wq0 = ux;
+            wq1 = uy;
+            wq2 = uz;
+            wt = (double)E;
+            walk = 2u;
           } else {
             if (kDebug) h_cr += 0x10000u;
             const float ct = thomson(st.uniform());
             const float uphi = st.uniform();
             rotate(ux, uy, uz, ct, uphi);
+          }
+          if constexpr (kElectrons) {
+            if (walk) {
+              float ex, ey, ez;
+              const double out = electron_walk(wq0, wq1, wq2, wt, walk == 2u, ex, ey, ez);
+              atomicAdd(&wa.ledger[walk == 2u ? NMD_LEDGER_DEP_POSITRON : 1], wt - out);
+              if (out > 0.0) {
+                atomicAdd(&wa.ledger[4], out);
+                if (kDebug) h_esc += out;
+              }
+              if (walk == 2u) {
+                atomicAdd(&wa.ledger[0], wt);  // the positron's kinetic energy, emitted
+                // the pair's tilt: two uniforms drawn with the positron (in
+                // the buffer this pass reserved)
+                const float u1 = st.uniform(), u2 = st.uniform();
+                if (out > 0.0) {
+                  // the positron left the grid: the pair is born outside it
+                  // and escapes, drawing nothing more
+                  atomicAdd(&wa.ledger[4], (double)P.nph * (double)kE0);
+                  if (kDebug) {
+                    h_esc += (double)P.nph * (double)kE0;
+                    h_pe_esc += P.nph << 16;
+                  } else {
+                    atomicAdd(&wa.stat[10], (unsigned long long)P.nph);
+                  }
+                  photon = P.nph - 1;
+                  pdone = true;
+                } else {
+                  // the pair is born where the positron stops: the first
+                  // photon along the decay's direction d, the second along
+                  // -d tilted by a Rayleigh-distributed angle
+                  sst[0][lane] = ex;
+                  sst[1][lane] = ey;
+                  sst[2][lane] = ez;
+                  photon = 0;
+                  start_photon();
+                  float wx = -ux, wy = -uy, wz = -uz;
+                  if (D->noncol_sigma > 0.0f) {
+                    const float th =
+                        D->noncol_sigma * __builtin_sqrtf(-2.0f * __logf(u1));
+                    float sth, cth;
+                    sincosf(th, &sth, &cth);
+                    rotate_sc(wx, wy, wz, cth, sth, u2);
+                  }
+                  // start_photon takes the second photon's direction negated
+                  sst[3][lane] = -wx;
+                  sst[4][lane] = -wy;
+                  sst[5][lane] = -wz;
+                }
+              }
+            }
           }
           if (dep >= 0.0) {
             atomicAdd(&wa.stat[7], 1ull);
