@@ -125,10 +125,60 @@ __device__ __forceinline__ void stage_halo(uint16_t *s, const Src &src, int cbas
   }
 }
 
+// The same staging split in two: this thread's share of the halo chunk into
+// registers (its global loads can then be in flight while the workgroup
+// computes on the chunk before), and from registers into LDS.
+template <int CC>
+constexpr int halo_regs() { return (HV * (CC / 8) + 255) / 256; }
+
+template <int CC>
+__device__ __forceinline__ void load_halo(u32x4_t (&rg)[halo_regs<CC>()], const Src &src, int cbase,
+                                          int nb, int D, int H, int W, int z0, int y0, int x0) {
+  constexpr int NC8 = CC / 8;
+  const bool first = cbase < src.c0;
+  const uint16_t *base = first ? src.x0 : src.x1;
+  const int cs = first ? src.c0 : src.c1;
+  const int coff = first ? cbase : cbase - src.c0;
+  const bool up = first && src.up0;
+  const int Ds = up ? (D + 1) >> 1 : D, Hs = up ? (H + 1) >> 1 : H, Ws = up ? (W + 1) >> 1 : W;
+#pragma unroll
+  for (int i = 0; i < halo_regs<CC>(); ++i) {
+    const int u = threadIdx.x + 256 * i;
+    const int hv = u / NC8, c8 = u - hv * NC8;
+    const int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
+    int z = z0 - 1 + hz, y = y0 - 1 + hy, x = x0 - 1 + hx;
+    u32x4_t val = {0u, 0u, 0u, 0u};
+    if (u < HV * NC8 && z >= 0 && z < D && y >= 0 && y < H && x >= 0 && x < W) {
+      if (up) {
+        z >>= 1;
+        y >>= 1;
+        x >>= 1;
+      }
+      const size_t vox = (((size_t)nb * Ds + z) * Hs + y) * Ws + x;
+      val = *reinterpret_cast<const u32x4_t *>(base + vox * cs + coff + c8 * 8);
+    }
+    rg[i] = val;
+  }
+}
+
+template <int CC>
+__device__ __forceinline__ void store_halo(uint16_t *s, const u32x4_t (&rg)[halo_regs<CC>()]) {
+  constexpr int NC8 = CC / 8;
+  constexpr int P = halo_pitch(CC);
+#pragma unroll
+  for (int i = 0; i < halo_regs<CC>(); ++i) {
+    const int u = threadIdx.x + 256 * i;
+    if (u < HV * NC8) {
+      const int hv = u / NC8, c8 = u - hv * NC8;
+      *reinterpret_cast<u32x4_t *>(s + hv * P + c8 * 8) = rg[i];
+    }
+  }
+}
+
 template <int CC, int NCB>
-// 16 input channels into one column block: four waves per SIMD (the plain K
-// loop fits 128 registers), which beats the pipelined loop at three
-__global__ __launch_bounds__(256, (NCB == 1 && CC == 16) ? 4 : 1) void conv_kernel(ConvArgs a) {
+// one column block: four waves per SIMD (the row-shared K loop with the
+// next chunk's halo in registers fits 128 registers)
+__global__ __launch_bounds__(256, (NCB == 1 && CC >= 16) ? 4 : 1) void conv_kernel(ConvArgs a) {
   constexpr int NC8 = CC / 8;
   constexpr int P = halo_pitch(CC);
   constexpr int NP = 27 * NC8;          // (tap, 8-channel group) pairs per chunk
@@ -155,9 +205,20 @@ __global__ __launch_bounds__(256, (NCB == 1 && CC == 16) ? 4 : 1) void conv_kern
     for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
   const int nchunks = a.cin / CC;
+  // the row-shared path holds the next chunk's halo in registers while it
+  // computes on this one
+  constexpr bool kPrefetch = NCB == 1 && CC >= 16;
+  u32x4_t pre[kPrefetch ? halo_regs<CC>() : 1];
+  if constexpr (kPrefetch) load_halo<CC>(pre, a.src, 0, nb, a.d, a.h, a.w_, z0, y0, x0);
   for (int ch = 0; ch < nchunks; ++ch) {
     if (ch) __syncthreads();
-    stage_halo<CC>(s_x, a.src, ch * CC, nb, a.d, a.h, a.w_, z0, y0, x0);
+    if constexpr (kPrefetch) {
+      store_halo<CC>(s_x, pre);
+      if (ch + 1 < nchunks)
+        load_halo<CC>(pre, a.src, (ch + 1) * CC, nb, a.d, a.h, a.w_, z0, y0, x0);
+    } else {
+      stage_halo<CC>(s_x, a.src, ch * CC, nb, a.d, a.h, a.w_, z0, y0, x0);
+    }
     __syncthreads();
     const uint16_t *wrow = a.w + (size_t)lx * 27 * a.cin + ch * CC;
     const size_t wcb = (size_t)16 * 27 * a.cin;  // one column block of weights
@@ -179,15 +240,38 @@ __global__ __launch_bounds__(256, (NCB == 1 && CC == 16) ? 4 : 1) void conv_kern
       for (int rb = 0; rb < 4; ++rb)
         av[rb] = *reinterpret_cast<const u32x4_t *>(s_x + rowoff[rb] + aoff);
     };
-    if constexpr (NCB == 1 && CC == 16) {
-#pragma unroll 2
-      for (int s = 0; s < NS; ++s) {
-        u32x4_t av[4], b[NCB];
-        load_step(s, av, b);
+    if constexpr (NCB == 1 && CC >= 16) {
+      // One column block: no A fragment serves two column blocks, so LDS
+      // reads would feed one MFMA each.  Instead K runs over (kz, kx, c8)
+      // with the three ky taps inside: the wave's 4 rows (one z, four
+      // consecutive y) and 3 ky shifts touch 6 halo rows, so 6 A fragments
+      // and 3 B fragments feed 12 MFMAs.
+      constexpr int NQ = 9 * NC8;          // (kz, kx, 8-channel group) triples
+      constexpr int NSQ = (NQ + 3) / 4;    // K steps of 32
+      const int r0w = wave * 4;            // the wave's first row
+      const int zr = r0w / TY, yb = r0w % TY;
+#pragma unroll 1
+      for (int sq = 0; sq < NSQ; ++sq) {
+        const int q = 4 * sq + g;
+        const bool valid = q < NQ;
+        const int qq = valid ? q : 0;
+        const int kzx = qq / NC8, c8 = qq - kzx * NC8;
+        const int kz = kzx / 3, kx = kzx - 3 * kz;
+        u32x4_t av[6], b[3];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int ky = 0; ky < 3; ++ky) {
+          const int tap = (kz * 3 + ky) * 3 + kx;
+          b[ky] = *reinterpret_cast<const u32x4_t *>(wrow + tap * a.cin + c8 * 8);
+          if (!valid) b[ky] = u32x4_t{0u, 0u, 0u, 0u};
+        }
+        const int abase = (((zr + kz) * HY + yb) * HX + lx + kx) * P + c8 * 8;
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mfma_bf16(av[rb], b[cb], acc[rb][cb]);
+        for (int j = 0; j < 6; ++j)
+          av[j] = *reinterpret_cast<const u32x4_t *>(s_x + abase + j * HX * P);
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) acc[rb][0] = mfma_bf16(av[rb + ky], b[ky], acc[rb][0]);
       }
       continue;
     }
