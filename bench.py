@@ -46,7 +46,7 @@ HBM_PEAK = 8.0e12  # bytes/s
 # WRITE_SIZE of rocprofv3 --pmc runs, scaled against a profiled 256 MiB copy
 # (profiles/transport_patient256x256x320_counters.md).  Only workloads whose
 # counters were taken with the current kernel have an entry.
-TRAFFIC_BYTES_PER_DECAY = {"patient": 1950.0}
+TRAFFIC_BYTES_PER_DECAY = {"patient": 1953.0}
 
 
 def valu_ops(stats):
@@ -586,7 +586,7 @@ def bench_denoiser(args):
 # 160x128x128 box): FETCH_SIZE x 2 + WRITE_SIZE of rocprofv3 --pmc runs
 # scaled against a profiled 256 MiB copy
 # (profiles/denoiser_conv_box160x128x128_counters.md)
-DENOISER_DOM_TRAFFIC_BYTES = (57974.7 * 2 + 81920.0) * 1024
+DENOISER_DOM_TRAFFIC_BYTES = (59646.1 * 2 + 81920.0) * 1024
 
 # HBM bytes of one ingest_kernel launch on the benchmark's CT: FETCH_SIZE x 2
 # + WRITE_SIZE of rocprofv3 --pmc runs scaled against a profiled 256 MiB copy
