@@ -174,8 +174,9 @@ def main():
                     help="plain MC and batch64 workloads: Woodcock majorant for the whole "
                          "phantom (global) or by region (the box of the dense voxels, and "
                          "the air around it)")
-    ap.add_argument("--phantoms", type=int, default=2,
-                    help="organ-time: held-out patients (seeds 20008 onward)")
+    ap.add_argument("--phantoms", type=int, default=20,
+                    help="organ-time: held-out patients (seeds 20008 onward; the "
+                         "metric's definition uses 100)")
     ap.add_argument("--weights", default=None,
                     help="organ-time: trained denoiser (.npz); default: the packaged one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -708,10 +709,21 @@ WEIGHTS = os.path.join(ROOT, "paper_2111_11687_amd", "weights", "unet16_patient.
 
 
 def bench_organ_time(args):
-    """Time to <= 1% organ dose on held-out patients (256x256x320):
-    plain Monte Carlo until 2 sigma <= 1% for every organ, against 10^7
-    decays + the trained denoiser + the Monte Carlo judge and fallback.  Both
-    results are compared with an untimed 10^9-decay reference."""
+    """Time to <= 1% organ dose, plain MC against MC + denoiser, on held-out
+    patients (256x256x320, seeds 20008 onward).
+
+    err(X) is the largest |X_o - R_o| / R_o over the 27 labelled organs, with
+    R an independent run of the same phantom: 10^10 decays, since at 10^9 the
+    reference's own standard error reaches 1.4% on the smallest organs, above
+    the 1% being tested.  Plain MC: every phantom runs the ladder
+    N = 10^6 * 2^k (k = 0..14, one continued run, so each rung is the
+    estimate after N decays); N_1% is the smallest rung where
+    err <= 1% on at least 95% of the phantoms, and T_MC the measured time of
+    fresh N_1% runs (transport and organ reduction).  MC + denoiser: T_DN is
+    the measured time of 10^7 decays, inference, the Monte Carlo judge and the
+    fallback where it triggers (capped at the ladder's top), with err on the
+    same phantoms.  value = T_MC / T_DN.  With --phantoms 100 this is the
+    definition's full sample; the default of 20 keeps the run to minutes."""
     import torch
     from paper_2111_11687_amd import binding as B
     from paper_2111_11687_amd import denoiser as DN
@@ -721,21 +733,43 @@ def bench_organ_time(args):
     eng = B.Engine(0)
     net = DN.UNet(eng)
     bias = net.load(args.weights or WEIGHTS)
-    tol = 0.01
-    rows = []
-    ws = None
-    for k in range(args.phantoms):
+    tol, n0, rungs, n_ref = 0.01, 10 ** 6, 15, 10 ** 10
+    ladder = [n0 << k for k in range(rungs)]
+    n_ph = args.phantoms
+    rows, ws = [], None
+    organs = slice(1, 28)  # labels 1..27 (28 is the rest of the body)
+    for k in range(n_ph):
         seed = 20008 + k
         prob = P.patient_phantom(seed=seed)
         if ws is None:
             ws = DN.Workspace(eng, prob.shape, train=False)
-        # warm-up of both paths on this phantom (allocations, first launches)
-        T.organ_dose_with_fallback(eng, net, prob, 2 * 10 ** 6, 5, bias, tol=1.0, ws=ws)
-        mc_org, mc_sig, mc_n, mc_s, mc_ok = T.plain_mc_to_tolerance(
-            eng, prob, 10 ** 7, seed + 3 * 10 ** 6, tol=tol, max_decays=2 * 10 ** 10)
+            # warm-up of both paths (allocations, first launches)
+            T.organ_dose_with_fallback(eng, net, prob, 2 * 10 ** 6, 5, bias, tol=1.0, ws=ws)
+        # reference: n_ref decays on an independent stream
+        eng.set_problem(T.PID_A, prob)
+        eng.run(T.PID_A, n_ref, seed + 2 * 10 ** 6)
+        ref, _, ref_sig = eng.organs(T.PID_A)
+        ref_map, _ = eng.dose(T.PID_A)
+        ref_h = ref_map.cpu().numpy()
+        del ref_map
+        present = ref[organs] > 0
+
+        def err(x):
+            r = ref[organs][present]
+            return float(np.max(np.abs(x[organs][present] - r) / r))
+
+        # the ladder, as one continued run
+        eng.set_problem(T.PID_A, prob)
+        errs, done = [], 0
+        for n in ladder:
+            eng.run(T.PID_A, n - done, seed + 3 * 10 ** 6)
+            done = n
+            errs.append(err(eng.organs(T.PID_A)[0]))
+        # MC + denoiser, timed
         dn = T.organ_dose_with_fallback(eng, net, prob, 10 ** 7, seed + 4 * 10 ** 6, bias,
-                                        tol=tol, ws=ws, max_decays=2 * 10 ** 10)
-        # voxel level (untimed): the 10^7 map and its denoised version
+                                        tol=tol, ws=ws, max_decays=ladder[-1])
+        # voxel level (untimed): the 10^7 map and its denoised version,
+        # mean |X_v - R_v| / R_v over voxels above 10% of the reference maximum
         eng.set_problem(T.PID_A, prob)
         eng.run(T.PID_A, 10 ** 7, seed + 10 ** 6)
         lo_map, _ = eng.dose(T.PID_A)
@@ -746,38 +780,38 @@ def bench_organ_time(args):
         t_inf = time.perf_counter() - t0
         lo_h, dn_h = lo_map.cpu().numpy(), dn_map.cpu().numpy()
         del lo_map, dn_map
-        eng.set_problem(T.PID_A, prob)
-        eng.run(T.PID_A, 10 ** 9, seed + 2 * 10 ** 6)
-        ref, _, ref_sig = eng.organs(T.PID_A)
-        ref_map, ref_rel = eng.dose(T.PID_A)
-        ref_h, rel_h = ref_map.cpu().numpy(), ref_rel.cpu().numpy()
-        del ref_map, ref_rel
-        body = prob.label > 0
-        m = body & (ref_h > 0.1 * ref_h[body].mean())
-        rms = lambda x: float(np.sqrt(np.mean(((x[m] - ref_h[m]) / ref_h[m]) ** 2)))  # noqa: E731
-        e_lo_v, e_dn_v = rms(lo_h), rms(dn_h)
-        e_ref_v = float(np.sqrt(np.mean(rel_h[m] ** 2)))
-        # Monte Carlo voxel error falls as N^-1/2: decays plain MC needs for
-        # the denoised map's error, the reference's own noise taken out
-        num, den = e_lo_v ** 2 - e_ref_v ** 2, e_dn_v ** 2 - e_ref_v ** 2
-        n_eq = 10 ** 7 * num / den if den > 0 else float("inf")
-        present = ref > 0  # organs with at least one voxel in this phantom
-        e_mc = np.abs(mc_org - ref)[present] / ref[present]
-        e_dn = np.abs(dn["organ"] - ref)[present] / ref[present]
-        row = {"seed": seed, "mc_s": mc_s, "mc_decays": mc_n, "mc_reached": mc_ok,
+        m = ref_h > 0.1 * ref_h.max()
+        verr = lambda x: float(np.mean(np.abs(x[m] - ref_h[m]) / ref_h[m]))  # noqa: E731
+        row = {"seed": seed, "ladder_err": errs, "dn_err": err(dn["organ"]),
                "dn_s": dn["seconds"], "dn_decays": dn["decays"], "dn_reached": dn["reached"],
                "dn_stage_s": dn["seconds_denoiser_stage"],
-               "organs_from_denoiser": int(sum(1 for x in dn["source"] if x == "denoiser")),
-               "mc_max_err": float(e_mc.max()), "dn_max_err": float(e_dn.max()),
-               "ref_max_sigma": float(ref_sig[present].max()),
+               "organs_from_denoiser": int(sum(1 for x in dn["source"][organs]
+                                               if x == "denoiser")),
+               "ref_max_rel_sigma": float(ref_sig[organs][present].max()),
                "organs_present": int(present.sum()),
-               "voxel_rms_rel_err_mc1e7": e_lo_v, "voxel_rms_rel_err_denoised": e_dn_v,
-               "voxel_rms_rel_sigma_ref1e9": e_ref_v, "voxel_equivalent_mc_decays": n_eq,
+               "voxel_err_mc1e7": verr(lo_h), "voxel_err_denoised": verr(dn_h),
                "inference_s": t_inf}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
-    t_mc = float(np.mean([r["mc_s"] for r in rows]))
+    need = int(np.ceil(0.95 * n_ph))
+    passing = [sum(1 for r in rows if r["ladder_err"][k] <= tol) for k in range(rungs)]
+    k1 = next((k for k in range(rungs) if passing[k] >= need), None)
+    n1 = ladder[k1] if k1 is not None else ladder[-1]
+    # T_MC: fresh runs of N_1% decays and the organ reduction, on up to three
+    # of the phantoms, measured
+    t_runs = []
+    for k in range(min(3, n_ph)):
+        prob = P.patient_phantom(seed=20008 + k)
+        eng.set_problem(T.PID_A, prob)
+        eng.sync()
+        t0 = time.perf_counter()
+        eng.run(T.PID_A, n1, 20008 + k + 5 * 10 ** 6)
+        eng.organs(T.PID_A)
+        eng.sync()
+        t_runs.append(time.perf_counter() - t0)
+    t_mc = float(np.mean(t_runs))
     t_dn = float(np.mean([r["dn_s"] for r in rows]))
+    dn_pass = sum(1 for r in rows if r["dn_err"] <= tol)
     out = {
         "metric": "time to <=1% organ dose: MC vs MC+denoiser",
         "value": t_mc / t_dn, "unit": "x (plain MC time / MC+denoiser time)",
@@ -785,12 +819,17 @@ def bench_organ_time(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "held-out patient phantoms 256x256x320 (seeds 20008+), 27 "
-                               "organs; plain MC until 2 sigma <= 1% for every organ vs 10^7 "
+                               "organs; err = max organ |X - R| / R against an independent "
+                               "10^10-decay run; plain MC on the ladder 10^6 * 2^k vs 10^7 "
                                "decays + U-Net denoiser + MC judge and fallback",
+                   "reference_decays": n_ref,
+                   "phantoms": n_ph, "ladder": ladder,
+                   "phantoms_within_1pct_per_rung": passing,
+                   "n_1pct_decays": n1 if k1 is not None else None,
+                   "n_1pct_reached": k1 is not None,
                    "mc_seconds": t_mc, "mc_denoiser_seconds": t_dn,
-                   "voxel_equivalent_mc_decays": float(np.median(
-                       [r["voxel_equivalent_mc_decays"] for r in rows])),
-                   "phantoms": rows},
+                   "mc_denoiser_phantoms_within_1pct": dn_pass,
+                   "rows": rows},
     }
     eng.close()
     print(json.dumps(out), flush=True)
