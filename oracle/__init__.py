@@ -27,7 +27,7 @@ RNG_PHILOX, RNG_XOSHIRO = 0, 1
 SRC_ACTIVITY, SRC_PENCIL = 0, 1
 
 LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded",
-                 "dep_positron")
+                 "dep_positron", "dep_beta")
 STATS_FIELDS = ("histories", "photons", "steps", "nulls", "compton", "photoelectric",
                 "rayleigh", "deposits", "merged", "max_merged", "escapes", "uniforms")
 HREC_FIELDS = ("edep", "escaped", "n_compton", "n_pe", "n_rayleigh", "n_steps",
@@ -67,12 +67,14 @@ class _Opts(ctypes.Structure):
                 ("n_threads", ctypes.c_int32), ("hist_out", ctypes.c_void_p),
                 ("electron_cutoff_mev", ctypes.c_double),
                 ("mean_excitation_ev", ctypes.c_void_p), ("rng", ctypes.c_int32),
-                ("positron", ctypes.c_int32), ("noncol_fwhm_rad", ctypes.c_double)]
+                ("positron", ctypes.c_int32), ("noncol_fwhm_rad", ctypes.c_double),
+                ("n_lines", ctypes.c_int32), ("line_mev", ctypes.c_void_p),
+                ("line_yield", ctypes.c_void_p), ("beta_mean_mev", ctypes.c_double)]
 
 
 class _Tally(ctypes.Structure):
     _fields_ = [("S", ctypes.c_void_p), ("S2", ctypes.c_void_p), ("O", ctypes.c_void_p),
-                ("O2", ctypes.c_void_p), ("ledger", ctypes.c_double * 7),
+                ("O2", ctypes.c_void_p), ("ledger", ctypes.c_double * 8),
                 ("stats", ctypes.c_uint64 * 12)]
 
 
@@ -319,7 +321,7 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
         tracking: int = TRACK_EXACT, kn_method: int | None = None, wide: bool | None = None,
         pencil=None, n_threads: int = 0, history_records: bool = False,
         electron_cutoff_mev: float = 0.0, mean_excitation_ev=None, rng: int | None = None,
-        positron: bool = False, noncol_fwhm_deg: float = 0.5):
+        positron: bool = False, noncol_fwhm_deg: float = 0.5, emitter=None):
     """Run n_hist histories; returns (tally, per-history records or None).
 
     ``pencil=(origin_cm, direction)`` selects a pencil-beam source.  The
@@ -333,6 +335,10 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
     straight CSDA walk, the pair born where it ends; needs
     ``mean_excitation_ev``) and tilts the second photon off back to back by
     a Rayleigh-distributed angle of FWHM ``noncol_fwhm_deg``.
+    ``emitter=(line_mev, line_yield, beta_mean_mev)`` replaces the photon
+    pair by a gamma + beta emitter: each decay emits at most one photon
+    (line i with probability line_yield[i]) and leaves beta_mean_mev in its
+    voxel.
     """
     if tally is None:
         tally = Tally(ph)
@@ -372,6 +378,13 @@ def run(ph: Phantom, n_hist: int, seed: int, tally: Tally | None = None, *,
     o.mean_excitation_ev = _ptr(iev)
     o.positron = int(bool(positron))
     o.noncol_fwhm_rad = float(np.radians(noncol_fwhm_deg))
+    if emitter is not None:
+        le = np.ascontiguousarray(emitter[0], dtype=np.float64)
+        ly = np.ascontiguousarray(emitter[1], dtype=np.float64)
+        if le.shape != ly.shape:
+            raise ValueError("one yield per line")
+        o.n_lines, o.line_mev, o.line_yield = le.size, _ptr(le), _ptr(ly)
+        o.beta_mean_mev = float(emitter[2])
     rc = lib().orc_run(ctypes.byref(ph._c), ctypes.byref(o), ctypes.byref(tally._c))
     if rc != 0:
         raise ValueError("oracle rejected the input (code %d)" % rc)

@@ -78,7 +78,8 @@
 #define ORC_POS_FLOOR 0.001 /* MeV: a positron's walk ends when its range above this runs out */
 #define ORC_POS_CDF_N 4096  /* intervals of the tabulated spectrum CDF */
 
-#define ORC_LEDGER_N 7
+#define ORC_LEDGER_N 8
+#define ORC_MAX_LINES 8
 #define ORC_STATS_N 12
 #define ORC_HREC_N 10
 
@@ -87,7 +88,8 @@ enum { ORC_KN_KAHN = 0, ORC_KN_BUTCHER = 1 };
 enum { ORC_SRC_ACTIVITY = 0, ORC_SRC_PENCIL = 1 };
 enum { ORC_EV_NULL = 0, ORC_EV_COMPTON = 1, ORC_EV_PE = 2, ORC_EV_RAYLEIGH = 3 };
 /* ledger slots */
-enum { L_EMIT = 0, L_DEP_C = 1, L_DEP_PE = 2, L_DEP_CUT = 3, L_ESC = 4, L_DISC = 5, L_DEP_POS = 6 };
+enum { L_EMIT = 0, L_DEP_C = 1, L_DEP_PE = 2, L_DEP_CUT = 3, L_ESC = 4, L_DISC = 5, L_DEP_POS = 6,
+       L_DEP_BETA = 7 };
 /* stats slots */
 enum {
   S_HIST = 0, S_PHOTONS = 1, S_STEPS = 2, S_NULL = 3, S_COMPTON = 4, S_PE = 5,
@@ -424,6 +426,15 @@ typedef struct {
                                      back to back; 1: 18F positron range and non-collinearity
                                      (needs mean_excitation_ev) */
   double noncol_fwhm_rad;         /* FWHM of the pair's deviation from back to back */
+  /* A gamma + beta emitter in place of the annihilation pair (n_lines > 0 or
+   * beta_mean_mev > 0; activity source only): a decay emits at most one
+   * photon, line i with probability line_yield[i] (the yields sum to at most
+   * 1), isotropic, of energy line_mev[i] (<= 0.511 MeV), and leaves
+   * beta_mean_mev in its voxel. */
+  int32_t n_lines;
+  const double *line_mev;
+  const double *line_yield;
+  double beta_mean_mev;
 } orc_opts;
 
 /* Accumulators.  S, S2: [nvox]; O, O2: [n_organs + 1]; all caller-owned
@@ -875,11 +886,11 @@ static int masked(const orc_opts *op, int ev)
 }
 
 static void photon_woodcock(const orc_ctx *cx, orc_stream *st, double r[3], double d[3],
-                            dep_list *l, orc_local *loc)
+                            double e0, dep_list *l, orc_local *loc)
 {
   const orc_phantom *ph = cx->ph;
   const int regions = cx->op->tracking == ORC_TRACK_REGIONS;
-  double E = ORC_E0_MEV;
+  double E = e0;
   double mur[8][3];
   double maj[2] = { 0.0, 0.0 }; /* inside the box, outside it */
   double e_cached = -1.0;
@@ -928,12 +939,12 @@ static void photon_woodcock(const orc_ctx *cx, orc_stream *st, double r[3], doub
 }
 
 static void photon_exact(const orc_ctx *cx, orc_stream *st, double r[3], int64_t iv[3], double d[3],
-                         dep_list *l, orc_local *loc)
+                         double e0, dep_list *l, orc_local *loc)
 {
   const orc_phantom *ph = cx->ph;
   const int32_t n[3] = { ph->nx, ph->ny, ph->nz };
   const double h[3] = { ph->dx, ph->dy, ph->dz };
-  double E = ORC_E0_MEV;
+  double E = e0;
   double mur[8][3];
   double e_cached = -1.0;
   int n_real = 0;
@@ -1179,6 +1190,36 @@ static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local 
     iv0[0] = (int64_t)floor(r0[0] / ph->dx);
     iv0[1] = (int64_t)floor(r0[1] / ph->dy);
     iv0[2] = (int64_t)floor(r0[2] / ph->dz);
+  } else if (op->n_lines > 0 || op->beta_mean_mev > 0.0) {
+    /* a gamma + beta emitter: the decay point, one uniform for the line
+     * (or none), the beta energy left in the decay voxel, then the photon */
+    sample_decay(cx, &st, iv0, r0);
+    const double u = stream_uniform(&st);
+    int line = -1;
+    double c = 0.0;
+    for (int i = 0; i < op->n_lines; ++i) {
+      c += op->line_yield[i];
+      if (u < c) {
+        line = i;
+        break;
+      }
+    }
+    if (op->beta_mean_mev > 0.0) {
+      const int64_t v0 = iv0[0] + (int64_t)ph->nx * (iv0[1] + (int64_t)ph->ny * iv0[2]);
+      loc->ledger[L_EMIT] += op->beta_mean_mev;
+      add_dep(l, loc, v0, op->beta_mean_mev, L_DEP_BETA);
+    }
+    if (line >= 0) {
+      const double e0 = op->line_mev[line];
+      sample_marsaglia(&st, d0);
+      loc->ledger[L_EMIT] += e0;
+      loc->stats[S_PHOTONS]++;
+      if (op->tracking != ORC_TRACK_EXACT)
+        photon_woodcock(cx, &st, r0, d0, e0, l, loc);
+      else
+        photon_exact(cx, &st, r0, iv0, d0, e0, l, loc);
+    }
+    nph = 0;
   } else {
     sample_decay(cx, &st, iv0, r0);
     sample_marsaglia(&st, d0);
@@ -1207,9 +1248,9 @@ static void run_history(const orc_ctx *cx, uint64_t hid, dep_list *l, orc_local 
         rotate_dir(d, cos(noncollinear_angle(op->noncol_fwhm_rad, u_dev[0])), u_dev[1]);
     }
     if (op->tracking != ORC_TRACK_EXACT)
-      photon_woodcock(cx, &st, r, d, l, loc);
+      photon_woodcock(cx, &st, r, d, ORC_E0_MEV, l, loc);
     else
-      photon_exact(cx, &st, r, iv, d, l, loc);
+      photon_exact(cx, &st, r, iv, d, ORC_E0_MEV, l, loc);
   }
   loc->stats[S_HIST]++;
   loc->stats[S_UNIFORMS] += st.n_uniform;
@@ -1275,6 +1316,20 @@ int orc_run(const orc_phantom *ph, const orc_opts *op, orc_tally *tal)
       if (!(op->mean_excitation_ev[m] > 0.0)) return -1;
   }
   if (op->positron && !(op->noncol_fwhm_rad >= 0.0 && op->noncol_fwhm_rad < 0.1)) return -1;
+  if (op->n_lines > 0 || op->beta_mean_mev > 0.0) {
+    if (op->positron || op->source_kind != ORC_SRC_ACTIVITY || op->n_lines > ORC_MAX_LINES ||
+        op->n_lines < 0 || !(op->beta_mean_mev >= 0.0) || (op->n_lines && (!op->line_mev ||
+        !op->line_yield)))
+      return -1;
+    double ysum = 0.0;
+    for (int i = 0; i < op->n_lines; ++i) {
+      if (!(op->line_mev[i] > 0.001 && op->line_mev[i] <= ORC_E0_MEV) ||
+          !(op->line_yield[i] >= 0.0))
+        return -1;
+      ysum += op->line_yield[i];
+    }
+    if (ysum > 1.0 + 1e-12) return -1;
+  }
   const int64_t nvox = (int64_t)ph->nx * ph->ny * ph->nz;
   for (int64_t v = 0; v < nvox; ++v) {
     if (ph->material[v] >= ph->n_mat || !(ph->density[v] > 0.0) || isinf(ph->density[v]))
