@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--positrons", action="store_true",
                     help="plain MC workloads: 18F positron range and the pair's "
                          "non-collinearity (FWHM 0.5 degrees)")
+    ap.add_argument("--emitter", choices=("pair", "lu177"), default="pair",
+                    help="plain MC workloads: the annihilation photon pair, or the 177Lu "
+                         "gamma lines and mean beta energy (tests/golden/lu177_decay.json)")
     ap.add_argument("--tracking", choices=("global", "regions"), default="global",
                     help="plain MC and batch64 workloads: Woodcock majorant for the whole "
                          "phantom (global) or by region (the box of the dense voxels, and "
@@ -256,6 +259,11 @@ def bench_mc(args):
     iev = [P.MEAN_EXCITATION_EV[next(k for k in P.MATERIALS
                                      if tuple(P.MATERIALS[k][:2]) == tuple(m))]
            for m in prob.materials]
+    if args.emitter == "lu177":
+        lu = json.load(open(os.path.join(ROOT, "tests", "golden", "lu177_decay.json")))
+        B.nmd_set_emitter(eng.ctx, 0, [e * 1e-3 for e in lu["gamma_lines_kev"]],
+                          lu["gamma_yields_per_decay"], lu["beta_minus_mean_kev"] * 1e-3)
+        what += "; 177Lu gamma lines and mean beta energy in place of the photon pair"
     if args.positrons:
         B.nmd_set_positron(eng.ctx, 0, True, 0.5, iev)
         what += "; 18F positrons walked (CSDA), pair non-collinearity 0.5 deg FWHM"
@@ -295,7 +303,8 @@ def bench_mc(args):
     led = eng.ledger(0)
     total = args.steps * nd
     value = total / dt
-    dep = led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"] + led["dep_positron"]
+    dep = (led["dep_compton"] + led["dep_pe"] + led["dep_cutoff"] + led["dep_positron"]
+           + led["dep_beta"])
     balance = (dep + led["escaped"] + led["discarded"]) / led["emitted"] - 1.0
     print(json.dumps({"steps_ms": [round(a.elapsed_time(b), 3) for a, b in evs],
                       "stats_per_decay": {k: v / total for k, v in stats.items()},
@@ -321,10 +330,11 @@ def bench_mc(args):
                    "photons_per_decay": prob.photons_per_decay,
                    "electron_cutoff_mev": args.electrons or None,
                    "tracking": args.tracking, "positrons": args.positrons,
+                   "emitter": args.emitter,
                    "tally": "f64", "transport": "f32"},
         "roofline": transport_roofline(per_decay, nd, kern_ms,
                                        None if args.electrons or args.positrons or
-                                       args.tracking != "global"
+                                       args.tracking != "global" or args.emitter != "pair"
                                        else TRAFFIC_BYTES_PER_DECAY.get(args.workload),
                                        ceilings),
     }

@@ -95,9 +95,12 @@ typedef struct {
  * ahead for a second step that a real collision or an escape then made
  * unnecessary.  With positrons on (nmd_set_positron), NMD_LEDGER_EMITTED
  * holds the photons' energy plus the positrons' kinetic energy, and
- * NMD_LEDGER_DEP_POSITRON what the positrons lost in the grid. */
+ * NMD_LEDGER_DEP_POSITRON what the positrons lost in the grid.  With an
+ * emitter (nmd_set_emitter), NMD_LEDGER_EMITTED holds the emitted photons'
+ * energy plus the beta energy, and NMD_LEDGER_DEP_BETA the beta energy. */
 enum { NMD_LEDGER_EMITTED = 0, NMD_LEDGER_DEP_COMPTON, NMD_LEDGER_DEP_PE, NMD_LEDGER_DEP_CUTOFF,
-       NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_DEP_POSITRON, NMD_LEDGER_N };
+       NMD_LEDGER_ESCAPED, NMD_LEDGER_DISCARDED, NMD_LEDGER_DEP_POSITRON, NMD_LEDGER_DEP_BETA,
+       NMD_LEDGER_N };
 enum { NMD_STAT_HISTORIES = 0, NMD_STAT_PHOTONS, NMD_STAT_STEPS, NMD_STAT_NULLS,
        NMD_STAT_COMPTON, NMD_STAT_PE, NMD_STAT_RAYLEIGH, NMD_STAT_DEPOSITS, NMD_STAT_MERGED,
        NMD_STAT_MAX_MERGED, NMD_STAT_ESCAPES, NMD_STAT_OVERFLOWS, NMD_STAT_CLAIMS,
@@ -186,6 +189,7 @@ nmd_status nmd_set_electrons(nmd_ctx *ctx, int32_t phantom_id, double cutoff_mev
  * direction, then one uniform for the kinetic energy, the positron's
  * direction and two uniforms for the tilt.  Pencil-beam runs emit no
  * positron.  on = 0 turns it off (mean_excitation_ev may then be NULL).
+ * Not together with nmd_set_emitter (NMD_E_STATE).
  * Independent of nmd_set_electrons: the positron tables run from 1 keV to
  * 640 keV.  Resets the phantom's tallies; re-registering the phantom drops
  * it; checkpoints do not record it; graphs captured before the call refuse
@@ -193,6 +197,25 @@ nmd_status nmd_set_electrons(nmd_ctx *ctx, int32_t phantom_id, double cutoff_mev
  * (arguments).  Synchronises the stream. */
 nmd_status nmd_set_positron(nmd_ctx *ctx, int32_t phantom_id, int32_t on, double noncol_fwhm_deg,
                             const double *mean_excitation_ev);
+
+/* Gamma + beta emitters in place of the annihilation pair (the other
+ * radionuclides Section 4 names, such as 177Lu).  With n_lines > 0 or
+ * beta_mean_mev > 0, every decay of the activity source emits at most one
+ * photon: line i, of energy energy_mev[i] in (0.001, 0.511] MeV (the
+ * cross-section grid ends at 511 keV), with probability yield[i] per decay
+ * (yields >= 0, summing to at most 1), in an isotropic direction; and it
+ * leaves beta_mean_mev, the mean beta kinetic energy, in the decay voxel
+ * (booked as NMD_LEDGER_DEP_BETA).  Per decay the draws are: the decay
+ * voxel and position, one uniform for the line (cumulative yields in line
+ * order; none above their sum), then the photon's direction.  n_lines (at
+ * most 8) = 0 with beta_mean_mev = 0 returns to the pair source.  Not
+ * together with nmd_set_positron (NMD_E_STATE).  Pencil-beam runs are
+ * unchanged.  Resets the phantom's tallies; re-registering the phantom drops
+ * it; checkpoints do not record it; graphs captured before the call refuse
+ * to launch.  energy_mev, yield: host double[n_lines].  Errors:
+ * NMD_E_STATE, NMD_E_INVALID.  Synchronises the stream. */
+nmd_status nmd_set_emitter(nmd_ctx *ctx, int32_t phantom_id, int32_t n_lines,
+                           const double *energy_mev, const double *yield, double beta_mean_mev);
 
 /* Woodcock tracking modes (the free flight of Section 2.1 samples collision
  * points against a majorant of the attenuation, with null collisions making

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnmdose.so")
 
 LEDGER_FIELDS = ("emitted", "dep_compton", "dep_pe", "dep_cutoff", "escaped", "discarded",
-                 "dep_positron")
+                 "dep_positron", "dep_beta")
 STATS_FIELDS = ("histories", "photons", "steps", "nulls", "compton", "photoelectric",
                 "rayleigh", "deposits", "merged", "max_merged", "escapes", "overflows",
                 "claims", "rng_blocks", "list_merges", "gathers")
@@ -83,7 +83,8 @@ EXPORTS = ("nmd_create", "nmd_destroy", "nmd_last_error", "nmd_set_stream",
            "nmd_debug_sample", "nmd_debug_sample_source", "nmd_debug_xs",
            "nmd_read_organ_dose", "nmd_get_last_launch", "nmd_graph_create",
            "nmd_graph_launch", "nmd_graph_destroy", "nmd_save", "nmd_load",
-           "nmd_set_electrons", "nmd_set_tracking", "nmd_set_positron") + NN_EXPORTS + \
+           "nmd_set_electrons", "nmd_set_tracking", "nmd_set_positron",
+           "nmd_set_emitter") + NN_EXPORTS + \
     INGEST_EXPORTS + PROBE_EXPORTS
 
 _lib = None
@@ -130,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "nmd_set_electrons": [vp, i32, d, vp],
         "nmd_set_tracking": [vp, i32, i32],
         "nmd_set_positron": [vp, i32, i32, d, vp],
+        "nmd_set_emitter": [vp, i32, i32, vp, vp, d],
         "nmd_load": [vp, i32, ctypes.c_char_p],
         "nmd_graph_destroy": [vp],
         "nmd_conv3d_fwd": [vp, i32, i32, i32, i32, ctypes.POINTER(nmd_nn_src), vp, vp, i32, i32,
@@ -294,6 +296,18 @@ def nmd_set_positron(ctx, phantom_id, on, noncol_fwhm_deg=0.5, mean_excitation_e
     _check(ctx, load_library().nmd_set_positron(
         ctx, int(phantom_id), int(bool(on)), float(noncol_fwhm_deg),
         None if arr is None else arr.ctypes.data_as(ctypes.c_void_p)))
+
+
+def nmd_set_emitter(ctx, phantom_id, line_mev=(), line_yield=(), beta_mean_mev=0.0):
+    """A gamma + beta emitter in place of the annihilation pair; no lines and
+    no beta energy return to the pair."""
+    e = np.ascontiguousarray(line_mev, dtype=np.float64)
+    y = np.ascontiguousarray(line_yield, dtype=np.float64)
+    if e.shape != y.shape:
+        raise ValueError("one yield per line")
+    _check(ctx, load_library().nmd_set_emitter(
+        ctx, int(phantom_id), int(e.size), e.ctypes.data_as(ctypes.c_void_p) if e.size else None,
+        y.ctypes.data_as(ctypes.c_void_p) if y.size else None, float(beta_mean_mev)))
 
 
 TRACKING = {"global": 0, "regions": 1}

@@ -79,6 +79,10 @@ struct Phantom {
   DevBuf p_cdf, p_guide, p_tab, p_inv_dr, p_slot;  // positron tables (nmd_set_positron)
   int32_t p_on = 0;
   float p_inv_dt = 0.0f, noncol_sigma = 0.0f;
+  int32_t em_n = 0;  // gamma + beta emitter (nmd_set_emitter): lines, or 0
+  bool em_on = false;
+  double em_cum[kMaxLines] = {};
+  float em_e[kMaxLines] = {}, em_beta = 0.0f;
   int32_t box0[3] = {0, 0, 0}, box1[3] = {0, 0, 0};  // inner box, voxel indices [box0, box1)
   double out_ratio = 0.0;  // outer majorant / inner majorant (0: no outer region)
   int32_t tracking = NMD_TRACK_GLOBAL;  // NMD_TRACK_* (nmd_set_tracking)
@@ -346,6 +350,13 @@ PhantomDesc make_desc(int32_t id, const Phantom &p) {
   d.p_tab = p.p_tab.as<float>();
   d.p_inv_dr = p.p_inv_dr.as<float>();
   d.p_slot = p.p_slot.as<uint8_t>();
+  d.em_on = p.em_on ? 1 : 0;
+  d.em_n = p.em_n;
+  for (int i = 0; i < kMaxLines; ++i) {
+    d.em_cum[i] = p.em_cum[i];
+    d.em_e[i] = p.em_e[i];
+  }
+  d.em_beta = p.em_beta;
   return d;
 }
 
@@ -491,7 +502,8 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
   for (int32_t i : ids) n_slots = std::max(n_slots, c->ph[i].n_org + 1);
   pl.debug = o.history_records != nullptr;
   pl.electrons = false;
-  for (int32_t i : ids) pl.electrons = pl.electrons || c->ph[i].e_cut > 0.0f || c->ph[i].p_on;
+  for (int32_t i : ids)
+    pl.electrons = pl.electrons || c->ph[i].e_cut > 0.0f || c->ph[i].p_on || c->ph[i].em_on;
   pl.regions = false;
   for (int32_t i : ids)
     pl.regions = pl.regions ||
@@ -1117,6 +1129,8 @@ nmd_status nmd_set_positron(nmd_ctx *c, int32_t id, int32_t on, double noncol_fw
   Phantom *p = find(c, id);
   if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
   if (on != 0 && on != 1) return fail(c, NMD_E_INVALID, "on must be 0 or 1");
+  if (on && p->em_on)
+    return fail(c, NMD_E_STATE, "phantom %d has an emitter in place of the positron's pair", id);
   if (!on) {
     p->p_cdf.release();
     p->p_guide.release();
@@ -1167,6 +1181,43 @@ nmd_status nmd_set_positron(nmd_ctx *c, int32_t id, int32_t on, double noncol_fw
     // Rayleigh scale sigma = FWHM / (2 sqrt(2 ln 2)) of the tilt's size
     p->noncol_sigma = (float)(noncol_fwhm_deg * M_PI / 180.0 / (2.0 * std::sqrt(2.0 * M_LN2)));
   }
+  p->gen = c->next_gen++;
+  if (p->has_activity && (s = zero_tallies(c, *p))) return s;
+  return upload_desc(c, id, *p);
+}
+
+nmd_status nmd_set_emitter(nmd_ctx *c, int32_t id, int32_t n_lines, const double *energy_mev,
+                           const double *yield, double beta_mean_mev) {
+  nmd_status s = check_ctx(c);
+  if (s) return s;
+  Phantom *p = find(c, id);
+  if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
+  if (n_lines < 0 || n_lines > kMaxLines)
+    return fail(c, NMD_E_INVALID, "an emitter has 0 to %d lines", kMaxLines);
+  if (!(beta_mean_mev >= 0.0 && beta_mean_mev < 10.0))
+    return fail(c, NMD_E_INVALID, "mean beta energy must lie in [0, 10) MeV");
+  if (n_lines && (!energy_mev || !yield))
+    return fail(c, NMD_E_INVALID, "line energies and yields are required");
+  double cum = 0.0;
+  for (int i = 0; i < n_lines; ++i) {
+    if (!(energy_mev[i] > 0.001 && energy_mev[i] <= 0.511))
+      return fail(c, NMD_E_INVALID, "line %d: energy must lie in (0.001, 0.511] MeV", i);
+    if (!(yield[i] >= 0.0)) return fail(c, NMD_E_INVALID, "line %d: negative yield", i);
+    cum += yield[i];
+  }
+  if (cum > 1.0 + 1e-12) return fail(c, NMD_E_INVALID, "the yields sum to more than 1");
+  const bool on = n_lines > 0 || beta_mean_mev > 0.0;
+  if (on && p->p_on)
+    return fail(c, NMD_E_STATE, "phantom %d emits positrons: turn them off first", id);
+  p->em_on = on;
+  p->em_n = on ? n_lines : 0;
+  cum = 0.0;
+  for (int i = 0; i < kMaxLines; ++i) {
+    if (i < p->em_n) cum += yield[i];  // summed in line order, as the decay's test reads it
+    p->em_cum[i] = i < p->em_n ? cum : 0.0;
+    p->em_e[i] = i < p->em_n ? (float)energy_mev[i] : 0.0f;
+  }
+  p->em_beta = on ? (float)beta_mean_mev : 0.0f;
   p->gen = c->next_gen++;
   if (p->has_activity && (s = zero_tallies(c, *p))) return s;
   return upload_desc(c, id, *p);
@@ -1411,8 +1462,9 @@ nmd_status nmd_get_ledger(nmd_ctx *c, int32_t id, double *ledger) {
   HIP_TRY(c, hipMemcpyAsync(l, p->ledger.p, sizeof l, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(st, p->stats.p, sizeof st, hipMemcpyDeviceToHost, c->stream));
   if ((s = sync(c))) return s;
-  // the photons' energy, and the positrons' kinetic energy counted on the device
-  ledger[0] = (double)st[NMD_STAT_PHOTONS] * (double)kE0 + l[0];
+  // the photons' energy, and the positrons' kinetic energy counted on the
+  // device; an emitter's photons and beta energy are all counted there
+  ledger[0] = (p->em_on ? 0.0 : (double)st[NMD_STAT_PHOTONS] * (double)kE0) + l[0];
   for (int i = 1; i < NMD_LEDGER_N; ++i) ledger[i] = l[i];
   return NMD_OK;
 }

@@ -30,6 +30,7 @@ constexpr int kMaxMaterials = 8;
 constexpr float kInnerRho = 0.01f;        // g/cm^3: voxels at least this dense lie in the inner box
 constexpr int kPosN = 4096;               // energy intervals of the positron spectrum's CDF
 constexpr double kF18T0 = 0.6335;         // MeV, 18F beta+ endpoint kinetic energy
+constexpr int kMaxLines = 8;              // gamma lines of an emitter
 constexpr float kPosFloor = 0.001f;       // MeV: a positron stops when its range above this runs out
 constexpr double kPosTop = 0.64;          // MeV: top of the positron range tables (endpoint 0.6335)
 
@@ -97,6 +98,14 @@ struct PhantomDesc {
   const float *p_tab;    // [kMaxMaterials][2][kETab]
   const float *p_inv_dr; // [kMaxMaterials]
   const uint8_t *p_slot; // [kMaxPalette]: palette index -> material slot
+  // gamma + beta emitter (em_on): line i of energy em_e[i] (MeV) when the
+  // decay's uniform u < em_cum[i] (cumulative yields, in FP64 as summed on
+  // the host), no photon above em_cum[em_n - 1]; em_beta (MeV) left in the
+  // decay voxel
+  int32_t em_on, em_n;
+  double em_cum[kMaxLines];
+  float em_e[kMaxLines];
+  float em_beta;
 };
 
 // Per-run fields of one phantom of a launch.

@@ -340,71 +340,6 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
     return tx + tau / mu_out;
   };
 
-  auto start_history = [&](unsigned long long rel) {
-    run_rel = rel;
-    st.start(hid0 + rel);
-    float o0, o1, o2, d0, d1, d2;
-    if (P.source_kind == 1) {
-      o0 = P.po[0];
-      o1 = P.po[1];
-      o2 = P.po[2];
-      d0 = P.pd[0];
-      d1 = P.pd[1];
-      d2 = P.pd[2];
-    } else {
-      // alias-table decay voxel: raw word for the column, uniform for the
-      // accept test, then a uniform position inside the voxel
-      const uint32_t x = st.word();
-      const uint32_t j = __umulhi(x, D->n_alias);
-      const float ua = st.uniform();
-      typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
-      const u32x4v av = G(reinterpret_cast<const u32x4v *>(D->alias))[j];
-      const uint4 a = make_uint4(av.x, av.y, av.z, av.w);
-      const uint32_t c = ua < __uint_as_float(a.x) ? a.y : a.z;  // x | y << 10 | z << 20
-      const uint32_t ix = c & 1023u, iy = (c >> 10) & 1023u, iz = c >> 20;
-      o0 = ((float)ix + st.uniform()) * D->dx;
-      o1 = ((float)iy + st.uniform()) * D->dy;
-      o2 = ((float)iz + st.uniform()) * D->dz;
-      marsaglia(st, d0, d1, d2);
-    }
-    sst[0][lane] = o0;
-    sst[1][lane] = o1;
-    sst[2][lane] = o2;
-    sst[3][lane] = d0;
-    sst[4][lane] = d1;
-    sst[5][lane] = d2;
-    photon = 0;
-    cnt = 0;
-    h_steps = h_nulls = h_cr = h_pe_esc = 0;
-    if (kDebug) h_esc = h_disc = 0.0;
-    if (kElectrons && D->p_on && P.source_kind != 1) {
-      // the positron: kinetic energy by inverting the spectrum's CDF
-      // (piecewise linear on kPosN intervals; the guide table gives the
-      // interval's neighbourhood), then its direction; its walk, and the
-      // pair's birth where it ends, wait for an interaction pass (event 4),
-      // as the walks of Compton electrons do
-      const float u = st.uniform();
-      const double ud = (double)u;
-      int k = (int)(u * (float)kPosN);
-      k = k > kPosN - 1 ? kPosN - 1 : k;
-      int i = G(D->p_guide)[k];
-      const double *cdf = D->p_cdf;
-      while (i < kPosN - 1 && G(cdf)[i + 1] <= ud) ++i;
-      const double c0 = G(cdf)[i], c1 = G(cdf)[i + 1];
-      const double f = c1 > c0 ? (ud - c0) / (c1 - c0) : 0.0;
-      E = (float)(((double)i + f) * (kF18T0 / kPosN));  // the positron's kinetic energy
-      marsaglia(st, ux, uy, uz);
-      px = o0;
-      py = o1;
-      pz = o2;
-      ev_t = 4;
-      state = kInteract;
-      return;
-    }
-    start_photon();
-    state = kFlight;
-  };
-
   // Score the history's merged deposits: voxel sums S, S2 and the
   // per-history organ scores q_o = sum_{v in o} e_v c / (m_v N_o).
   auto flush_list = [&](bool final_flush) {
@@ -785,6 +720,117 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
     }
   };
 
+  // Start history rel of the wave's chunk in this lane: its decay point and
+  // photon direction (or a pending positron), and its first photon.
+  auto start_history = [&](unsigned long long rel) {
+    run_rel = rel;
+    st.start(hid0 + rel);
+    float o0, o1, o2, d0, d1, d2;
+    if (P.source_kind == 1) {
+      o0 = P.po[0];
+      o1 = P.po[1];
+      o2 = P.po[2];
+      d0 = P.pd[0];
+      d1 = P.pd[1];
+      d2 = P.pd[2];
+    } else {
+      // alias-table decay voxel: raw word for the column, uniform for the
+      // accept test, then a uniform position inside the voxel
+      const uint32_t x = st.word();
+      const uint32_t j = __umulhi(x, D->n_alias);
+      const float ua = st.uniform();
+      typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+      const u32x4v av = G(reinterpret_cast<const u32x4v *>(D->alias))[j];
+      const uint4 a = make_uint4(av.x, av.y, av.z, av.w);
+      const uint32_t c = ua < __uint_as_float(a.x) ? a.y : a.z;  // x | y << 10 | z << 20
+      const uint32_t ix = c & 1023u, iy = (c >> 10) & 1023u, iz = c >> 20;
+      o0 = ((float)ix + st.uniform()) * D->dx;
+      o1 = ((float)iy + st.uniform()) * D->dy;
+      o2 = ((float)iz + st.uniform()) * D->dz;
+      if (kElectrons && D->em_on) {
+        // a gamma + beta emitter: one uniform picks the line (or none), the
+        // beta energy stays in the decay voxel, then the photon's direction
+        const double ul = (double)st.uniform();
+        int line = -1;
+        for (int i = 0; i < D->em_n; ++i)
+          if (line < 0 && ul < D->em_cum[i]) line = i;
+        sst[0][lane] = o0;
+        sst[1][lane] = o1;
+        sst[2][lane] = o2;
+        cnt = 0;
+        h_steps = h_nulls = h_cr = h_pe_esc = 0;
+        if (kDebug) h_esc = h_disc = 0.0;
+        if (D->em_beta > 0.0f) {
+          const uint32_t v0 = ix + (uint32_t)D->nx * (iy + (uint32_t)D->ny * iz);
+          atomicAdd(&wa.ledger[0], (double)D->em_beta);
+          atomicAdd(&wa.ledger[NMD_LEDGER_DEP_BETA], (double)D->em_beta);
+          atomicAdd(&wa.stat[7], 1ull);
+          deposit(v0, (uint32_t)G(D->rec)[v0], (double)D->em_beta);
+        }
+        if (line < 0) {  // no photon: the history ends here
+          photon = P.nph;
+          state = kPhotonEnd;
+          return;
+        }
+        marsaglia(st, d0, d1, d2);
+        // one photon: start_photon takes the last photon of a pair, which it
+        // negates
+        const float sg = P.nph > 1 ? -1.0f : 1.0f;
+        sst[3][lane] = sg * d0;
+        sst[4][lane] = sg * d1;
+        sst[5][lane] = sg * d2;
+        photon = P.nph - 1;
+        start_photon();
+        E = D->em_e[line];
+        atomicAdd(&wa.ledger[0], (double)E);
+        ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+        if (kRegions && (psteps & kOuter)) {
+          ep.mu_hat *= D->out_ratio;
+          ep.inv_mu_ln2 *= D->inv_out_ratio;
+        }
+        state = kFlight;
+        return;
+      }
+      marsaglia(st, d0, d1, d2);
+    }
+    sst[0][lane] = o0;
+    sst[1][lane] = o1;
+    sst[2][lane] = o2;
+    sst[3][lane] = d0;
+    sst[4][lane] = d1;
+    sst[5][lane] = d2;
+    photon = 0;
+    cnt = 0;
+    h_steps = h_nulls = h_cr = h_pe_esc = 0;
+    if (kDebug) h_esc = h_disc = 0.0;
+    if (kElectrons && D->p_on && P.source_kind != 1) {
+      // the positron: kinetic energy by inverting the spectrum's CDF
+      // (piecewise linear on kPosN intervals; the guide table gives the
+      // interval's neighbourhood), then its direction; its walk, and the
+      // pair's birth where it ends, wait for an interaction pass (event 4),
+      // as the walks of Compton electrons do
+      const float u = st.uniform();
+      const double ud = (double)u;
+      int k = (int)(u * (float)kPosN);
+      k = k > kPosN - 1 ? kPosN - 1 : k;
+      int i = G(D->p_guide)[k];
+      const double *cdf = D->p_cdf;
+      while (i < kPosN - 1 && G(cdf)[i + 1] <= ud) ++i;
+      const double c0 = G(cdf)[i], c1 = G(cdf)[i + 1];
+      const double f = c1 > c0 ? (ud - c0) / (c1 - c0) : 0.0;
+      E = (float)(((double)i + f) * (kF18T0 / kPosN));  // the positron's kinetic energy
+      marsaglia(st, ux, uy, uz);
+      px = o0;
+      py = o1;
+      pz = o2;
+      ev_t = 4;
+      state = kInteract;
+      return;
+    }
+    start_photon();
+    state = kFlight;
+  };
+
   // Claim histories for the idle lanes from the wave's chunk, claiming new
   // chunks (or switching phantom once the wave has drained) as needed.
   auto refill = [&]() {
@@ -1029,7 +1075,10 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
           state = kFlight;
         } else {
           atomicAdd(&wa.stat[0], 1ull);
-          atomicAdd(&wa.stat[1], (unsigned long long)P.nph);
+          // an emitter's decay has one photon or none (photon == P.nph)
+          atomicAdd(&wa.stat[1], (unsigned long long)((kElectrons && D->em_on)
+                                                          ? (photon < P.nph ? 1u : 0u)
+                                                          : P.nph));
           if (kDebug) {
             atomicAdd(&wa.stat[2], (unsigned long long)h_steps);
             atomicAdd(&wa.stat[3], (unsigned long long)h_nulls);

@@ -176,9 +176,11 @@ __device__ __forceinline__ void store_halo(uint16_t *s, const u32x4_t (&rg)[halo
 }
 
 template <int CC, int NCB>
-// one column block: four waves per SIMD (the row-shared K loop with the
-// next chunk's halo in registers fits 128 registers)
-__global__ __launch_bounds__(256, (NCB == 1 && CC >= 16) ? 4 : 1) void conv_kernel(ConvArgs a) {
+// one column block of 16-channel chunks: four waves per SIMD (the row-shared
+// K loop with the next chunk's halo in registers fits 128 registers); with
+// 32-channel chunks the halo's LDS allows two
+__global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1)) : 1) void conv_kernel(
+    ConvArgs a) {
   constexpr int NC8 = CC / 8;
   constexpr int P = halo_pitch(CC);
   constexpr int NP = 27 * NC8;          // (tap, 8-channel group) pairs per chunk

@@ -1,0 +1,90 @@
+"""Gamma + beta emitters on the device (nmd_set_emitter), with the 177Lu
+data of tests/golden/lu177_decay.json: history by history against the
+oracle's emitter on the same streams, statistically against exact traversal
+on the patient, and the switch's semantics."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from conftest import ledger_balance, oracle_phantom
+from paper_2111_11687_amd import binding as B
+from paper_2111_11687_amd import phantoms as P
+
+pytestmark = pytest.mark.gpu
+LU = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lu177_decay.json")))
+LINES = [e * 1e-3 for e in LU["gamma_lines_kev"]]
+YIELDS = LU["gamma_yields_per_decay"]
+BETA = LU["beta_minus_mean_kev"] * 1e-3
+
+
+def _balance(led):
+    return ledger_balance(led) + led["dep_beta"] / led["emitted"]
+
+
+def test_emitter_replays_history_by_history(engine, orc):
+    """The slab's point source: the line choice, the beta deposit and the
+    photon's events replay the oracle's emitter draw for draw."""
+    prob = P.slab_phantom(n=64, voxel_mm=6.0)
+    engine.set_problem(61, prob)
+    B.nmd_set_emitter(engine.ctx, 61, LINES, YIELDS, BETA)
+    n = 30_000
+    t = engine.torch
+    rec = t.zeros(n * 10, dtype=t.float64, device=engine.device)
+    engine.run(61, n, 41, history_records=rec)
+    g = rec.cpu().numpy().reshape(n, 10)
+    tal, o = orc.run(oracle_phantom(orc, prob), n, 41, tracking=orc.TRACK_WOODCOCK, pid=61,
+                     history_records=True, emitter=(LINES, YIELDS, BETA))
+    same = np.all(g[:, [2, 3, 4, 5, 8]] == o[:, [2, 3, 4, 5, 8]], axis=1)
+    assert same.mean() >= 0.995, same.mean()
+    e_ok = np.abs(g[:, 0] - o[:, 0]) <= 1e-5 + 1e-5 * np.abs(o[:, 0])
+    x_ok = np.abs(g[:, 1] - o[:, 1]) <= 1e-5 + 1e-5 * np.abs(o[:, 1])
+    assert (same & e_ok & x_ok).mean() >= 0.995
+    led = engine.ledger(61)
+    assert abs(_balance(led)) < 1e-9 and abs(_balance(tal.ledger)) < 1e-9
+    assert led["dep_beta"] == pytest.approx(n * BETA, rel=1e-6)
+    st = engine.stats(61)
+    assert st["photons"] == tal.stats["photons"]
+    assert abs(st["photons"] / n - sum(YIELDS)) < 5 * np.sqrt(sum(YIELDS) / n)
+
+
+def test_emitter_statistical_parity_patient(engine, orc):
+    """The full-size patient with the 177Lu emitter against the
+    exact-traversal oracle with the same emitter: every organ within three
+    combined sigma."""
+    prob = P.patient_phantom()
+    engine.set_problem(62, prob)
+    B.nmd_set_emitter(engine.ctx, 62, LINES, YIELDS, BETA)
+    engine.run(62, 10 ** 7, 9001)
+    gr, _, gs = engine.organs(62)
+    led = engine.ledger(62)
+    assert abs(_balance(led)) < 1e-9
+    ph = oracle_phantom(orc, prob)
+    tal, _ = orc.run(ph, 4 * 10 ** 6, 9002, emitter=(LINES, YIELDS, BETA))
+    orr, os_ = orc.organ_mean_sigma(tal, prob.total_activity_bq)
+    m = (gr > 0) & (orr > 0)
+    z = (gr[m] - orr[m]) / np.sqrt((gr[m] * gs[m]) ** 2 + (orr[m] * os_[m]) ** 2)
+    print("emitter organ z:", np.round(z, 2))
+    assert m.sum() >= 10 and np.all(np.abs(z) <= 3.0)
+
+
+def test_emitter_switch_and_validation(engine):
+    prob = P.patient_phantom(shape=(50, 40, 40), voxel_mm=(12.0, 12.0, 18.0), seed=45)
+    engine.set_problem(62, prob)
+    for bad in (([0.6], [0.1], 0.1), ([0.1], [0.7, 0.5][:1] + [0.0], 0.1),
+                ([0.1, 0.2], [0.6, 0.5], 0.1), ([0.1], [0.1], -0.1)):
+        with pytest.raises((B.NmdError, ValueError)):
+            B.nmd_set_emitter(engine.ctx, 62, *bad)
+    B.nmd_set_emitter(engine.ctx, 62, LINES, YIELDS, BETA)
+    with pytest.raises(B.NmdError, match="NMD_E_STATE"):
+        B.nmd_set_positron(engine.ctx, 62, True, 0.5, [75.0] * len(prob.materials))
+    engine.run(62, 100_000, 3)
+    led = engine.ledger(62)
+    assert led["dep_beta"] == pytest.approx(100_000 * BETA, rel=1e-6)
+    B.nmd_set_emitter(engine.ctx, 62)  # back to the photon pair
+    assert engine.stats(62)["histories"] == 0
+    engine.run(62, 100_000, 3)
+    led = engine.ledger(62)
+    assert led["dep_beta"] == 0.0
+    assert led["emitted"] == pytest.approx(100_000 * 2 * 0.511, rel=1e-6)
