@@ -482,6 +482,18 @@ nmd_status plan_run(nmd_ctx *c, int32_t id, uint64_t n, uint64_t seed, const nmd
       if (kv.second.has_activity || o.source_kind == 1) ids.push_back(kv.first);
     if (ids.empty()) return fail(c, NMD_E_STATE, "no phantom has an activity map");
     if (o.history_records) return fail(c, NMD_E_INVALID, "history_records needs a single phantom");
+    // largest first: the work queue hands out a phantom's chunks in this
+    // order, so the launch ends on the cheapest histories.  A history's cost
+    // grows with the path a photon takes to leave the grid; the grid's
+    // diagonal stands for it.  Results do not depend on the order (each
+    // history's stream is keyed by seed, phantom and history).
+    auto diag = [&](int32_t i) {
+      const Phantom &p = c->ph[i];
+      const double a = p.nx * p.dx, b = p.ny * p.dy, d = p.nz * p.dz;
+      return a * a + b * b + d * d;
+    };
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int32_t x, int32_t y) { return diag(x) > diag(y); });
   } else {
     Phantom *p = find(c, id);
     if (!p) return fail(c, NMD_E_STATE, "phantom %d is not registered", id);
