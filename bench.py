@@ -33,8 +33,8 @@ sys.path.insert(0, ROOT)
 VALU_PER_PHILOX_BLOCK = 53
 VALU_PER_UNIFORM = 4
 VALU_PER_STEP = 34      # free flight, inside test, voxel index, record gather, event choice
-VALU_PER_COMPTON = 193  # one Klein-Nishina attempt, azimuth, rotation, energy factors
-VALU_PER_RAYLEIGH = 106  # Thomson angle and rotation
+VALU_PER_COMPTON = 95   # one Klein-Nishina attempt, azimuth, rotation, energy factors
+VALU_PER_RAYLEIGH = 81  # Thomson angle and rotation
 VALU_PER_HISTORY = 40   # alias voxel, position in the voxel, one Marsaglia attempt
 VALU_PER_MERGED = 10    # tally address, e^2; the two FP64 atomics are counted apart
 # FP32 vector peak 157.3 TFLOP/s = 78.6 T FMA lane-operations/s (256 CUs x
@@ -46,7 +46,7 @@ HBM_PEAK = 8.0e12  # bytes/s
 # WRITE_SIZE of rocprofv3 --pmc runs, scaled against a profiled 256 MiB copy
 # (profiles/transport_patient256x256x320_counters.md).  Only workloads whose
 # counters were taken with the current kernel have an entry.
-TRAFFIC_BYTES_PER_DECAY = {"patient": 1953.0}
+TRAFFIC_BYTES_PER_DECAY = {"patient": 1950.0}
 
 
 def valu_ops(stats):

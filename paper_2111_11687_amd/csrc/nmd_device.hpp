@@ -10,6 +10,12 @@ namespace nmd {
 
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+// v_rcp_f32 and v_sqrt_f32: about an ulp from the rounded results, one
+// instruction each where IEEE-rounded division and square root take about a
+// dozen.  The samplers below and the transport use them on normal operands;
+// their outputs then differ from the rounded ones in the last bits only.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies (one v_mad_u64_u32 each) with a Weyl-sequence key
@@ -145,7 +151,7 @@ __device__ __forceinline__ void marsaglia(S &st, float &dx, float &dy, float &dz
     v2 = 2.0f * st.uniform() - 1.0f;
     s = v1 * v1 + v2 * v2;
   } while (s >= 1.0f);
-  const float q = 2.0f * __builtin_sqrtf(1.0f - s);
+  const float q = 2.0f * fast_sqrt(1.0f - s);
   dx = v1 * q;
   dy = v2 * q;
   dz = 1.0f - 2.0f * s;
@@ -160,21 +166,21 @@ __device__ __forceinline__ void marsaglia(S &st, float &dx, float &dy, float &dz
 template <class S>
 __device__ __forceinline__ bool klein_nishina_try(S &st, float k, float &eps, float &cost) {
   const float a = 1.0f + 2.0f * k;
-  const float eps0 = 1.0f / a;
+  const float eps0 = fast_rcp(a);
   const float e02 = eps0 * eps0;
   const float a1 = fast_log2(a) * 0.69314718055994531f;  // ln(1 + 2k)
   const float a2 = 0.5f * (1.0f - e02);
-  const float inv_k = 1.0f / k;
+  const float inv_k = fast_rcp(k);
   const float r1 = st.uniform();
   const float r2 = st.uniform();
   const float r3 = st.uniform();
   if (r1 * (a1 + a2) < a1)
     eps = fast_exp2(-a1 * r2 * 1.4426950408889634f);
   else
-    eps = __builtin_sqrtf(e02 + (1.0f - e02) * r2);
-  const float t = (1.0f - eps) * inv_k / eps;
+    eps = fast_sqrt(e02 + (1.0f - e02) * r2);
+  const float t = (1.0f - eps) * inv_k * fast_rcp(eps);
   const float sin2 = t * (2.0f - t);
-  const float g = 1.0f - eps * sin2 / (1.0f + eps * eps);
+  const float g = 1.0f - eps * sin2 * fast_rcp(1.0f + eps * eps);
   cost = 1.0f - t;
   return r3 < g;
 }
@@ -205,7 +211,7 @@ __device__ __forceinline__ void rotate_sc(float &ux, float &uy, float &uz, float
   const float cphi = __builtin_amdgcn_cosf(uphi);  // argument in revolutions
   const float sphi = __builtin_amdgcn_sinf(uphi);
   const float sg = uz >= 0.0f ? 1.0f : -1.0f;
-  const float a = -1.0f / (sg + uz);
+  const float a = -fast_rcp(sg + uz);
   const float b = ux * uy * a;
   const float sc = sint * cphi, ss = sint * sphi;
   const float nu = cost * ux + sc * (1.0f + sg * ux * ux * a) + ss * b;
@@ -220,7 +226,7 @@ __device__ __forceinline__ void rotate_sc(float &ux, float &uy, float &uz, float
 // The same with sin(theta) = sqrt(1 - cos^2(theta)), for angles that are not
 // small (small ones lose their digits there and pass the sine instead).
 __device__ __forceinline__ void rotate(float &ux, float &uy, float &uz, float cost, float uphi) {
-  rotate_sc(ux, uy, uz, cost, __builtin_sqrtf(fmaxf(0.0f, 1.0f - cost * cost)), uphi);
+  rotate_sc(ux, uy, uz, cost, fast_sqrt(fmaxf(0.0f, 1.0f - cost * cost)), uphi);
 }
 
 // Energy-dependent factors: mu_C = cC * sig, mu_PE = cPE * gpe, mu_R = cR * gr
@@ -242,8 +248,8 @@ __device__ __forceinline__ EnergyParams energy_params(float E, const float *ln2_
   const float m0 = ln2_maj[i], m1 = ln2_maj[i + 1];
   p.sig = fast_exp2(k0 + f * (k1 - k0));
   p.mu_hat = kKappa * fast_exp2(m0 + f * (m1 - m0));
-  p.inv_mu_ln2 = 0.69314718055994531f / p.mu_hat;
-  const float ie = 1.0f / E;
+  p.inv_mu_ln2 = 0.69314718055994531f * fast_rcp(p.mu_hat);
+  const float ie = fast_rcp(E);
   p.gr = ie * ie;
   p.gpe = p.gr * ie;
   return p;

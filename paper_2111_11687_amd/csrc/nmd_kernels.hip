@@ -288,9 +288,9 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
   // ep.mu_hat / ep.inv_mu_ln2 to the end point's region.  Without an outer
   // region a ray leaving the box leaves the grid.
   //
-  // Distances to the box faces multiply by v_rcp_f32 reciprocals (within an
-  // ulp) rather than dividing: a wave whose lanes diverge runs both walks
-  // below, and the rounded divisions cost 3% of the whole run.
+  // Distances to the box faces multiply by reciprocals (fast_rcp) rather
+  // than dividing: a wave whose lanes diverge runs both walks below, and the
+  // rounded divisions cost 3% of the whole run.
   //
   // From inside (photons on their way out of the body), the ray leaves at
   // the box's exit distance tf and the rest of the step stretches by
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const float b = u[a] > 0.0f ? d->bcm1[a] : d->bcm0[a];
-      const float ta = u[a] != 0.0f ? (b - p[a]) * __builtin_amdgcn_rcpf(u[a]) : 3.0e38f;
+      const float ta = u[a] != 0.0f ? (b - p[a]) * fast_rcp(u[a]) : 3.0e38f;
       tf = fminf(tf, fmaxf(ta, 0.0f));
     }
     psteps |= kOuter;
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (u[a] != 0.0f) {
-        const float iu = __builtin_amdgcn_rcpf(u[a]);
+        const float iu = fast_rcp(u[a]);
         const float t1 = (d->bcm0[a] - p[a]) * iu, t2 = (d->bcm1[a] - p[a]) * iu;
         tn = fmaxf(tn, fminf(t1, t2));
         tf = fminf(tf, fmaxf(t1, t2));
@@ -339,10 +339,10 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
       psteps &= ~kOuter;
       ep.mu_hat = mu_in;
       ep.inv_mu_ln2 *= d->out_ratio;
-      return te + tau * __builtin_amdgcn_rcpf(mu_in);
+      return te + tau * fast_rcp(mu_in);
     }
     tau -= mu_in * (tx - te);
-    return tx + tau * __builtin_amdgcn_rcpf(mu_out);
+    return tx + tau * fast_rcp(mu_out);
   };
 
   // Score the history's merged deposits: voxel sums S, S2 and the
@@ -650,12 +650,12 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
     for (int a = 0; a < 3; ++a) {
       if (qv[a] > 0.0f) {
         sp[a] = 1;
-        tn[a] = ((float)(iv[a] + 1) * h[a] - pos[a]) / qv[a];
-        td[a] = h[a] / qv[a];
+        tn[a] = ((float)(iv[a] + 1) * h[a] - pos[a]) * fast_rcp(qv[a]);
+        td[a] = h[a] * fast_rcp(qv[a]);
       } else if (qv[a] < 0.0f) {
         sp[a] = -1;
-        tn[a] = ((float)iv[a] * h[a] - pos[a]) / qv[a];
-        td[a] = -h[a] / qv[a];
+        tn[a] = ((float)iv[a] * h[a] - pos[a]) * fast_rcp(qv[a]);
+        td[a] = -h[a] * fast_rcp(qv[a]);
       } else {
         sp[a] = 0;
         tn[a] = __builtin_inff();
