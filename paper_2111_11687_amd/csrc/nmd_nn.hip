@@ -70,9 +70,14 @@ struct Src {
 // ---------------------------------------------------------------------------
 // Forward / backward-data convolution
 // ---------------------------------------------------------------------------
-constexpr int TX = 16, TY = 8, TZ = 2;                 // output tile (256 voxels)
-constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;   // halo tile
-constexpr int HV = HX * HY * HZ;                       // 720 voxels
+// Output tile: 16 x 8 voxels in x and y, TZ planes in z (2, or 4 for the
+// kernel with one column block of 16-channel chunks), one voxel of halo.
+constexpr int TX = 16, TY = 8;
+constexpr int HX = TX + 2, HY = TY + 2;
+template <int TZ>
+constexpr int halo_vox() { return HX * HY * (TZ + 2); }  // 720 or 1080 voxels
+template <int CC, int NCB>
+constexpr int conv_tz() { return NCB == 1 && CC == 16 ? 4 : 2; }
 
 // LDS voxel pitch (elements): 8 consecutive lanes reading 16 bytes at this
 // stride cover all 32 four-byte bank groups once.
@@ -96,7 +101,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return (b & 7) * (n >> 3) + (b >> 3);
 }
 
-template <int CC>
+template <int CC, int TZ>
 __device__ __forceinline__ void stage_halo(uint16_t *s, const Src &src, int cbase, int nb, int D,
                                            int H, int W, int z0, int y0, int x0) {
   constexpr int NC8 = CC / 8;
@@ -107,7 +112,7 @@ __device__ __forceinline__ void stage_halo(uint16_t *s, const Src &src, int cbas
   const int coff = first ? cbase : cbase - src.c0;
   const bool up = first && src.up0;
   const int Ds = up ? (D + 1) >> 1 : D, Hs = up ? (H + 1) >> 1 : H, Ws = up ? (W + 1) >> 1 : W;
-  for (int u = threadIdx.x; u < HV * NC8; u += 256) {
+  for (int u = threadIdx.x; u < halo_vox<TZ>() * NC8; u += 256) {
     const int hv = u / NC8, c8 = u - hv * NC8;
     const int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
     int z = z0 - 1 + hz, y = y0 - 1 + hy, x = x0 - 1 + hx;
@@ -128,11 +133,11 @@ __device__ __forceinline__ void stage_halo(uint16_t *s, const Src &src, int cbas
 // The same staging split in two: this thread's share of the halo chunk into
 // registers (its global loads can then be in flight while the workgroup
 // computes on the chunk before), and from registers into LDS.
-template <int CC>
-constexpr int halo_regs() { return (HV * (CC / 8) + 255) / 256; }
+template <int CC, int TZ>
+constexpr int halo_regs() { return (halo_vox<TZ>() * (CC / 8) + 255) / 256; }
 
-template <int CC>
-__device__ __forceinline__ void load_halo(u32x4_t (&rg)[halo_regs<CC>()], const Src &src, int cbase,
+template <int CC, int TZ>
+__device__ __forceinline__ void load_halo(u32x4_t (&rg)[(halo_regs<CC, TZ>())], const Src &src, int cbase,
                                           int nb, int D, int H, int W, int z0, int y0, int x0) {
   constexpr int NC8 = CC / 8;
   const bool first = cbase < src.c0;
@@ -142,13 +147,13 @@ __device__ __forceinline__ void load_halo(u32x4_t (&rg)[halo_regs<CC>()], const 
   const bool up = first && src.up0;
   const int Ds = up ? (D + 1) >> 1 : D, Hs = up ? (H + 1) >> 1 : H, Ws = up ? (W + 1) >> 1 : W;
 #pragma unroll
-  for (int i = 0; i < halo_regs<CC>(); ++i) {
+  for (int i = 0; i < halo_regs<CC, TZ>(); ++i) {
     const int u = threadIdx.x + 256 * i;
     const int hv = u / NC8, c8 = u - hv * NC8;
     const int hz = hv / (HY * HX), r = hv - hz * (HY * HX), hy = r / HX, hx = r - hy * HX;
     int z = z0 - 1 + hz, y = y0 - 1 + hy, x = x0 - 1 + hx;
     u32x4_t val = {0u, 0u, 0u, 0u};
-    if (u < HV * NC8 && z >= 0 && z < D && y >= 0 && y < H && x >= 0 && x < W) {
+    if (u < halo_vox<TZ>() * NC8 && z >= 0 && z < D && y >= 0 && y < H && x >= 0 && x < W) {
       if (up) {
         z >>= 1;
         y >>= 1;
@@ -161,14 +166,14 @@ __device__ __forceinline__ void load_halo(u32x4_t (&rg)[halo_regs<CC>()], const 
   }
 }
 
-template <int CC>
-__device__ __forceinline__ void store_halo(uint16_t *s, const u32x4_t (&rg)[halo_regs<CC>()]) {
+template <int CC, int TZ>
+__device__ __forceinline__ void store_halo(uint16_t *s, const u32x4_t (&rg)[(halo_regs<CC, TZ>())]) {
   constexpr int NC8 = CC / 8;
   constexpr int P = halo_pitch(CC);
 #pragma unroll
-  for (int i = 0; i < halo_regs<CC>(); ++i) {
+  for (int i = 0; i < halo_regs<CC, TZ>(); ++i) {
     const int u = threadIdx.x + 256 * i;
-    if (u < HV * NC8) {
+    if (u < halo_vox<TZ>() * NC8) {
       const int hv = u / NC8, c8 = u - hv * NC8;
       *reinterpret_cast<u32x4_t *>(s + hv * P + c8 * 8) = rg[i];
     }
@@ -176,16 +181,19 @@ __device__ __forceinline__ void store_halo(uint16_t *s, const u32x4_t (&rg)[halo
 }
 
 template <int CC, int NCB>
-// one column block of 16-channel chunks: four waves per SIMD (the row-shared
-// K loop with the next chunk's halo in registers fits 128 registers); with
-// 32-channel chunks the halo's LDS allows two
-__global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1)) : 1) void conv_kernel(
+// one column block of 16-channel chunks: a 4-plane tile whose 50.6 KB halo
+// lets three workgroups share a CU; with 32-channel chunks the 2-plane
+// halo's LDS allows two
+__global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 3 : (CC == 32 ? 2 : 1)) : 1) void conv_kernel(
     ConvArgs a) {
   constexpr int NC8 = CC / 8;
   constexpr int P = halo_pitch(CC);
   constexpr int NP = 27 * NC8;          // (tap, 8-channel group) pairs per chunk
   constexpr int NS = (NP + 3) / 4;      // K steps of 32
-  __shared__ __align__(16) uint16_t s_x[HV * P];
+  constexpr int TZ = conv_tz<CC, NCB>();
+  constexpr int RW = TZ * TY / 4;       // output rows (z, y) per wave: 4 or 8
+  __shared__ __align__(16) uint16_t s_x[halo_vox<TZ>() * P];
+  static_assert(RW == 4 || (NCB == 1 && CC >= 16), "wide rows only in the row-shared loop");
 
   const int nb = blockIdx.y;
   const int t = xcd_tile(blockIdx.x, a.n_tiles);
@@ -200,9 +208,9 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1))
     const int r = wave * 4 + rb;
     rowoff[rb] = (((r / TY) * HY + (r % TY)) * HX + lx) * P;
   }
-  f32x4_t acc[4][NCB];
+  f32x4_t acc[RW][NCB];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < RW; ++rb)
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
@@ -210,16 +218,16 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1))
   // the row-shared path holds the next chunk's halo in registers while it
   // computes on this one
   constexpr bool kPrefetch = NCB == 1 && CC >= 16;
-  u32x4_t pre[kPrefetch ? halo_regs<CC>() : 1];
-  if constexpr (kPrefetch) load_halo<CC>(pre, a.src, 0, nb, a.d, a.h, a.w_, z0, y0, x0);
+  u32x4_t pre[kPrefetch ? halo_regs<CC, TZ>() : 1];
+  if constexpr (kPrefetch) load_halo<CC, TZ>(pre, a.src, 0, nb, a.d, a.h, a.w_, z0, y0, x0);
   for (int ch = 0; ch < nchunks; ++ch) {
     if (ch) __syncthreads();
     if constexpr (kPrefetch) {
-      store_halo<CC>(s_x, pre);
+      store_halo<CC, TZ>(s_x, pre);
       if (ch + 1 < nchunks)
-        load_halo<CC>(pre, a.src, (ch + 1) * CC, nb, a.d, a.h, a.w_, z0, y0, x0);
+        load_halo<CC, TZ>(pre, a.src, (ch + 1) * CC, nb, a.d, a.h, a.w_, z0, y0, x0);
     } else {
-      stage_halo<CC>(s_x, a.src, ch * CC, nb, a.d, a.h, a.w_, z0, y0, x0);
+      stage_halo<CC, TZ>(s_x, a.src, ch * CC, nb, a.d, a.h, a.w_, z0, y0, x0);
     }
     __syncthreads();
     const uint16_t *wrow = a.w + (size_t)lx * 27 * a.cin + ch * CC;
@@ -245,12 +253,12 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1))
     if constexpr (NCB == 1 && CC >= 16) {
       // One column block: no A fragment serves two column blocks, so LDS
       // reads would feed one MFMA each.  Instead K runs over (kz, kx, c8)
-      // with the three ky taps inside: the wave's 4 rows (one z, four
-      // consecutive y) and 3 ky shifts touch 6 halo rows, so 6 A fragments
-      // and 3 B fragments feed 12 MFMAs.
+      // with the three ky taps inside: the wave's RW rows (one z, RW
+      // consecutive y) and 3 ky shifts touch RW + 2 halo rows, so RW + 2 A
+      // fragments and 3 B fragments feed 3 RW MFMAs (24 for a whole plane).
       constexpr int NQ = 9 * NC8;          // (kz, kx, 8-channel group) triples
       constexpr int NSQ = (NQ + 3) / 4;    // K steps of 32
-      const int r0w = wave * 4;            // the wave's first row
+      const int r0w = wave * RW;           // the wave's first row
       const int zr = r0w / TY, yb = r0w % TY;
 #pragma unroll 1
       for (int sq = 0; sq < NSQ; ++sq) {
@@ -259,7 +267,7 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1))
         const int qq = valid ? q : 0;
         const int kzx = qq / NC8, c8 = qq - kzx * NC8;
         const int kz = kzx / 3, kx = kzx - 3 * kz;
-        u32x4_t av[6], b[3];
+        u32x4_t av[RW + 2], b[3];
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
           const int tap = (kz * 3 + ky) * 3 + kx;
@@ -268,12 +276,12 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1))
         }
         const int abase = (((zr + kz) * HY + yb) * HX + lx + kx) * P + c8 * 8;
 #pragma unroll
-        for (int j = 0; j < 6; ++j)
+        for (int j = 0; j < RW + 2; ++j)
           av[j] = *reinterpret_cast<const u32x4_t *>(s_x + abase + j * HX * P);
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-          for (int rb = 0; rb < 4; ++rb) acc[rb][0] = mfma_bf16(av[rb + ky], b[ky], acc[rb][0]);
+          for (int rb = 0; rb < RW; ++rb) acc[rb][0] = mfma_bf16(av[rb + ky], b[ky], acc[rb][0]);
       }
       continue;
     }
@@ -307,8 +315,8 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 4 : (CC == 32 ? 2 : 1))
 
   // epilogue: bias, ReLU, mask, round to bf16
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    const int r = wave * 4 + rb;
+  for (int rb = 0; rb < RW; ++rb) {
+    const int r = wave * RW + rb;
     const int z = z0 + r / TY, y = y0 + r % TY;
     if (z >= a.d || y >= a.h) continue;
     const size_t rowvox = (((size_t)nb * a.d + z) * a.h + y) * a.w_;
@@ -967,10 +975,11 @@ nmd_status run_conv(nmd_ctx *c, int n, int d, int h, int w, const Src &src, int 
   a.relu = relu;
   a.tiles_x = (w + TX - 1) / TX;
   a.tiles_y = (h + TY - 1) / TY;
-  a.tiles_z = (d + TZ - 1) / TZ;
-  a.n_tiles = a.tiles_x * a.tiles_y * a.tiles_z;
   const int cc = chunk_of(cin);
   const int ncb = cout / 16;
+  const int tz = cc == 16 && ncb == 1 ? conv_tz<16, 1>() : 2;  // matches conv_tz
+  a.tiles_z = (d + tz - 1) / tz;
+  a.n_tiles = a.tiles_x * a.tiles_y * a.tiles_z;
   hipStream_t s = ctx_stream(c);
   hipError_t e = hipErrorInvalidValue;
   if (cc == 8 && ncb == 1) e = launch_conv_t<8, 1>(a, n, s);
