@@ -200,7 +200,9 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 3 : (CC == 32 ? 2 : 1))
   constexpr int TZ = conv_tz<CC, NCB>();
   constexpr int RW = TZ * TY / 4;       // output rows (z, y) per wave: 4 or 8
   __shared__ __align__(16) uint16_t s_x[halo_vox<TZ>() * P];
-  static_assert(RW == 4 || (NCB == 1 && CC >= 16), "wide rows only in the row-shared loop");
+  // the row-shared K loop: one column block, or several of 16-channel chunks
+  constexpr bool kRowShared = CC >= 16 && (NCB == 1 || CC == 16);
+  static_assert(RW == 4 || kRowShared, "wide rows only in the row-shared loop");
 
   const int nb = blockIdx.y;
   const int t = xcd_tile(blockIdx.x, a.n_tiles);
@@ -257,12 +259,13 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 3 : (CC == 32 ? 2 : 1))
       for (int rb = 0; rb < 4; ++rb)
         av[rb] = *reinterpret_cast<const u32x4_t *>(s_x + rowoff[rb] + aoff);
     };
-    if constexpr (NCB == 1 && CC >= 16) {
-      // One column block: no A fragment serves two column blocks, so LDS
-      // reads would feed one MFMA each.  Instead K runs over (kz, kx, c8)
-      // with the three ky taps inside: the wave's RW rows (one z, RW
-      // consecutive y) and 3 ky shifts touch RW + 2 halo rows, so RW + 2 A
-      // fragments and 3 B fragments feed 3 RW MFMAs (24 for a whole plane).
+    if constexpr (kRowShared) {
+      // K runs over (kz, kx, c8) with the three ky taps inside: the wave's
+      // RW rows (one z, RW consecutive y) and 3 ky shifts touch RW + 2 halo
+      // rows, so RW + 2 A fragments and 3 NCB B fragments feed 3 RW NCB
+      // MFMAs (24 for a whole plane and one column block, 36 for four rows
+      // and three).  With one column block no A fragment would otherwise
+      // serve two MFMAs.
       constexpr int NQ = 9 * NC8;          // (kz, kx, 8-channel group) triples
       constexpr int NSQ = (NQ + 3) / 4;    // K steps of 32
       const int r0w = wave * RW;           // the wave's first row
@@ -274,12 +277,15 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 3 : (CC == 32 ? 2 : 1))
         const int qq = valid ? q : 0;
         const int kzx = qq / NC8, c8 = qq - kzx * NC8;
         const int kz = kzx / 3, kx = kzx - 3 * kz;
-        u32x4_t av[RW + 2], b[3];
+        u32x4_t av[RW + 2], b[3][NCB];
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
           const int tap = (kz * 3 + ky) * 3 + kx;
-          b[ky] = *reinterpret_cast<const u32x4_t *>(wrow + tap * a.cin + c8 * 8);
-          if (!valid) b[ky] = u32x4_t{0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) {
+            b[ky][cb] = *reinterpret_cast<const u32x4_t *>(wrow + cb * wcb + tap * a.cin + c8 * 8);
+            if (!valid) b[ky][cb] = u32x4_t{0u, 0u, 0u, 0u};
+          }
         }
         const int abase = (((zr + kz) * HY + yb) * HX + lx + kx) * P + c8 * 8;
 #pragma unroll
@@ -288,7 +294,10 @@ __global__ __launch_bounds__(256, NCB == 1 ? (CC == 16 ? 3 : (CC == 32 ? 2 : 1))
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-          for (int rb = 0; rb < RW; ++rb) acc[rb][0] = mfma_bf16(av[rb + ky], b[ky], acc[rb][0]);
+          for (int rb = 0; rb < RW; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              acc[rb][cb] = mfma_bf16(av[rb + ky], b[ky][cb], acc[rb][cb]);
       }
       continue;
     }
