@@ -361,8 +361,12 @@ constexpr int WTX = 16, WTY = 4, WTZ = 2;                  // voxel tile (128)
 constexpr int WHX = WTX + 2, WHY = WTY + 2, WHZ = WTZ + 2;  // halo
 constexpr int WHV = WHX * WHY * WHZ;                       // 432
 constexpr int WXP = 24;                                    // halo row pitch
-constexpr int WCP = WHZ * WHY * WXP + 8;                   // halo channel pitch (584)
-constexpr int WDP = WTX * WTY * WTZ + 8;                   // dy channel pitch (136)
+// Channel pitches of 2 mod 4 sixteen-byte quads: lane groups g and g + 1,
+// which a ds_read_b128 serves in one cycle (lanes 0-7 with 24-31, 8-15
+// with 16-23), then fall on the even and the odd bank quads.
+constexpr int WCP = WHZ * WHY * WXP + 16;                  // halo channel pitch (592)
+constexpr int WDP = WTX * WTY * WTZ + 16;                  // dy channel pitch (144)
+static_assert((WCP / 8) % 4 == 2 && (WDP / 8) % 4 == 2, "conflict-free channel pitches");
 
 struct WgradArgs {
   Src src;
