@@ -597,7 +597,7 @@ def bench_denoiser(args):
 # 160x128x128 box): FETCH_SIZE x 2 + WRITE_SIZE of rocprofv3 --pmc runs
 # scaled against a profiled 256 MiB copy
 # (profiles/denoiser_conv_box160x128x128_counters.md)
-DENOISER_DOM_TRAFFIC_BYTES = (59646.1 * 2 + 81920.0) * 1024
+DENOISER_DOM_TRAFFIC_BYTES = (79671.7 * 2 + 81920.2) * 1024
 
 # HBM bytes of one ingest_kernel launch on the benchmark's CT: FETCH_SIZE x 2
 # + WRITE_SIZE of rocprofv3 --pmc runs scaled against a profiled 256 MiB copy
