@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=("patient", "slab", "water", "paper101", "batch64",
                                            "denoiser", "organ-time", "ingest", "ceilings",
-                                           "units"),
+                                           "units", "lds"),
                     default="patient",
                     help="patient: the 256x256x320 phantom (the headline metric); slab, water, "
                          "paper101: the other plain MC phantoms; batch64: 64 "
@@ -213,6 +213,8 @@ def main():
         return bench_ceilings(args)
     if args.workload == "units":
         return bench_units(args)
+    if args.workload == "lds":
+        return bench_lds(args)
     return bench_mc(args)
 
 
@@ -401,6 +403,30 @@ def bench_units(args):
            "data": "synthetic",
            "config": {"workload": "unit_kernel<0..7>: %d workgroups x 256 lanes x %d units"
                                   % (blocks, iters), "launch_ms": ms}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_lds(args):
+    """One dispatch of the LDS probe per lane pattern, reads then writes
+    (1024 workgroups x 256 lanes x 256 accesses); their SQ_LDS_BANK_CONFLICT
+    and SQ_INSTS_LDS counters give the bank conflicts of each pattern."""
+    from paper_2111_11687_amd import binding as B
+    eng = B.Engine(0)
+    iters, blocks = 256, 1024
+    ms = {}
+    for write in (False, True):
+        for p in B.LDS_PATTERNS:
+            key = ("write " if write else "read ") + p
+            B.nmd_probe_lds(eng.ctx, p, write, 4, 16)  # warm-up
+            ms[key] = B.nmd_probe_lds(eng.ctx, p, write, iters, blocks)
+            print(json.dumps({key: ms[key]}), file=sys.stderr, flush=True)
+    eng.close()
+    out = {"metric": "LDS probe launch time", "value": sum(ms.values()), "unit": "ms",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": sum(ms.values()),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic",
+           "config": {"workload": "16-byte LDS reads and writes, %d workgroups x 256 lanes x %d "
+                                  "accesses per lane pattern" % (blocks, iters), "launch_ms": ms}}
     print(json.dumps(out), flush=True)
 
 

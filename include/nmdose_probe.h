@@ -69,6 +69,37 @@ enum {
 nmd_status nmd_probe_unit(nmd_ctx *ctx, int32_t kind, uint32_t iters, uint32_t blocks,
                           double *ms);
 
+/* LDS lane patterns: the byte offset of lane L (lx = L mod 16, g = L / 16)
+ * of one 16-byte LDS access, as the convolutions' fragment reads and halo
+ * stores make them. */
+enum {
+  NMD_LDS_CONTIGUOUS = 0,     /* 16 L                                      */
+  NMD_LDS_HALO48 = 1,         /* 48 lx + 48 (g / 2) + 16 (g mod 2): a 16-channel
+                                 halo read at a 48-byte voxel pitch           */
+  NMD_LDS_P48_SAME = 2,       /* 48 lx (the four lane groups read alike)    */
+  NMD_LDS_P48_FAR = 3,        /* 48 lx + 768 g                              */
+  NMD_LDS_P80_G16 = 4,        /* 80 lx + 16 g                               */
+  NMD_LDS_P48_LANE = 5,       /* 48 L                                       */
+  NMD_LDS_GROUP_MAJOR = 6,    /* 16 lx + 256 g                              */
+  NMD_LDS_P64_G16 = 7,        /* 64 lx + 16 g                               */
+  NMD_LDS_HALO32 = 8,         /* 32 lx + 32 (g / 2) + 16 (g mod 2): the same read
+                                 at a 32-byte pitch                          */
+  NMD_LDS_P48_G16 = 9,        /* 48 lx + 16 g                               */
+  NMD_LDS_STORE48 = 10,       /* 48 (L / 2) + 16 (L mod 2): a 16-channel halo
+                                 store at a 48-byte pitch                    */
+  NMD_LDS_P96_G16 = 11,       /* 96 lx + 16 g                               */
+  NMD_LDS_N = 12
+};
+
+/* Launch `blocks` workgroups (1..65536) of four waves whose lanes each make
+ * `iters` (1..2^16) 16-byte LDS accesses at the offsets of `pattern` (plus a
+ * multiple of 4 KiB that varies with the iteration), reads when `write` is 0
+ * and writes otherwise; *ms (may be NULL) receives the launch time.  Bank
+ * conflicts per access are SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS of the
+ * dispatch. */
+nmd_status nmd_probe_lds(nmd_ctx *ctx, int32_t pattern, int32_t write, uint32_t iters,
+                         uint32_t blocks, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,10 +58,13 @@ NN_EXPORTS = ("nmd_conv3d_fwd", "nmd_conv3d_bwd_data", "nmd_conv3d_bwd_weight", 
 
 INGEST_EXPORTS = ("nmd_resample_linear", "nmd_ct_to_phantom", "nmd_ct_ingest")
 
-PROBE_EXPORTS = ("nmd_probe_ceiling", "nmd_probe_unit")
+PROBE_EXPORTS = ("nmd_probe_ceiling", "nmd_probe_unit", "nmd_probe_lds")
 CEILINGS = {"copy": 0, "atomic_f64": 1, "gather_u16": 2, "valu_fma": 3, "mul64": 4,
             "mfma_bf16": 5}
 UNITS = ("loop", "philox", "uniform", "step", "compton", "rayleigh", "history", "merged")
+# NMD_LDS_* lane patterns, in enum order
+LDS_PATTERNS = ("contiguous", "halo48", "p48_same", "p48_far", "p80_g16", "p48_lane",
+                "group_major", "p64_g16", "halo32", "p48_g16", "store48", "p96_g16")
 
 
 class nmd_grid(ctypes.Structure):
@@ -159,6 +162,7 @@ def load_library(path: str = LIB_PATH):
         "nmd_probe_ceiling": [vp, i32, u64, ctypes.c_uint32, ctypes.POINTER(d),
                               ctypes.POINTER(d)],
         "nmd_probe_unit": [vp, i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(d)],
+        "nmd_probe_lds": [vp, i32, i32, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(d)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -517,6 +521,16 @@ def nmd_probe_unit(ctx, kind, iters, blocks):
     k = UNITS.index(kind) if isinstance(kind, str) else int(kind)
     ms = ctypes.c_double()
     _check(ctx, load_library().nmd_probe_unit(ctx, k, iters, blocks, ctypes.byref(ms)))
+    return ms.value
+
+
+def nmd_probe_lds(ctx, pattern, write=False, iters=256, blocks=1024):
+    """Launch time (ms) of the LDS probe over `pattern` (an LDS_PATTERNS name
+    or number), reads or writes."""
+    k = LDS_PATTERNS.index(pattern) if isinstance(pattern, str) else int(pattern)
+    ms = ctypes.c_double()
+    _check(ctx, load_library().nmd_probe_lds(ctx, k, int(bool(write)), iters, blocks,
+                                             ctypes.byref(ms)))
     return ms.value
 
 

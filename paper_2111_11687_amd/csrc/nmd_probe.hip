@@ -247,6 +247,55 @@ __global__ __launch_bounds__(256) void unit_kernel(UnitArgs A) {
   if (acc == 0x5bd1e995u) A.out[0] = acc;  // keeps the work; practically never true
 }
 
+// LDS lane patterns (NMD_LDS_*): byte offset of lane L's 16-byte access.
+constexpr int kLdsQuads = 2048;  // 32 KiB of 16-byte quads
+__host__ __device__ inline uint32_t lds_offset(int p, int L) {
+  const int lx = L & 15, g = L >> 4;
+  switch (p) {
+    case NMD_LDS_CONTIGUOUS: return 16 * L;
+    case NMD_LDS_HALO48: return 48 * lx + 48 * (g >> 1) + 16 * (g & 1);
+    case NMD_LDS_P48_SAME: return 48 * lx;
+    case NMD_LDS_P48_FAR: return 48 * lx + 768 * g;
+    case NMD_LDS_P80_G16: return 80 * lx + 16 * g;
+    case NMD_LDS_P48_LANE: return 48 * L;
+    case NMD_LDS_GROUP_MAJOR: return 16 * lx + 256 * g;
+    case NMD_LDS_P64_G16: return 64 * lx + 16 * g;
+    case NMD_LDS_HALO32: return 32 * lx + 32 * (g >> 1) + 16 * (g & 1);
+    case NMD_LDS_P48_G16: return 48 * lx + 16 * g;
+    case NMD_LDS_STORE48: return 48 * (L >> 1) + 16 * (L & 1);
+    case NMD_LDS_P96_G16: return 96 * lx + 16 * g;
+  }
+  return 0;
+}
+
+// Each iteration adds (it mod 4) x 4 KiB: the same banks, a fresh address,
+// so that no access can be folded into another.
+__global__ __launch_bounds__(256) void lds_read_kernel(int p, uint32_t iters, uint32_t *out) {
+  __shared__ u32x4_t s[kLdsQuads];
+  for (int i = threadIdx.x; i < kLdsQuads; i += 256) s[i] = u32x4_t{(uint32_t)i, 1u, 2u, 3u};
+  __syncthreads();
+  const uint32_t q = lds_offset(p, threadIdx.x & 63) / 16;
+  u32x4_t acc = {0u, 0u, 0u, 0u};
+  for (uint32_t it = 0; it < iters; ++it) {
+    acc += s[q + ((it & 3u) << 8)];
+    __asm__ volatile("" ::: "memory");
+  }
+  out[threadIdx.x & 63] = acc.x ^ acc.y ^ acc.z ^ acc.w;
+}
+
+__global__ __launch_bounds__(256) void lds_write_kernel(int p, uint32_t iters, uint32_t *out) {
+  __shared__ u32x4_t s[kLdsQuads];
+  const uint32_t q = lds_offset(p, threadIdx.x & 63) / 16;
+  u32x4_t v = {threadIdx.x, 1u, 2u, 3u};
+  for (uint32_t it = 0; it < iters; ++it) {
+    v.x += 1u;
+    s[q + ((it & 3u) << 8)] = v;
+    __asm__ volatile("" ::: "memory");
+  }
+  __syncthreads();
+  out[threadIdx.x & 63] = s[threadIdx.x].x;
+}
+
 }  // namespace
 }  // namespace nmd
 
@@ -422,6 +471,40 @@ nmd_status nmd_probe_unit(nmd_ctx *c, int32_t kind, uint32_t iters, uint32_t blo
   if ((s = ctx_hip(c, hipEventRecord(t.a, st), "hipEventRecord"))) return s;
   hipLaunchKernelGGL(fns[kind], dim3(blocks), dim3(256), 0, st, A);
   if ((s = ctx_hip(c, hipGetLastError(), "unit_kernel"))) return s;
+  if ((s = ctx_hip(c, hipEventRecord(t.b, st), "hipEventRecord"))) return s;
+  if ((s = ctx_hip(c, hipEventSynchronize(t.b), "hipEventSynchronize"))) return s;
+  float el = 0.0f;
+  if ((s = ctx_hip(c, hipEventElapsedTime(&el, t.a, t.b), "hipEventElapsedTime"))) return s;
+  if (ms) *ms = el;
+  return NMD_OK;
+}
+
+nmd_status nmd_probe_lds(nmd_ctx *c, int32_t pattern, int32_t write, uint32_t iters,
+                         uint32_t blocks, double *ms) {
+  nmd_status s = ctx_enter(c);
+  if (s) return s;
+  if (pattern < 0 || pattern >= NMD_LDS_N) return ctx_fail(c, NMD_E_INVALID, "unknown LDS pattern");
+  if (iters == 0 || iters > (1u << 16) || blocks == 0 || blocks > 65536)
+    return ctx_fail(c, NMD_E_INVALID, "iters in 1..2^16 and blocks in 1..65536 required");
+  // every lane's quads (the pattern's offset plus up to 3 x 4 KiB) stay in
+  // the 32 KiB array
+  for (int L = 0; L < 64; ++L)
+    if (lds_offset(pattern, L) % 16 || lds_offset(pattern, L) / 16 + (3u << 8) >= (uint32_t)kLdsQuads)
+      return ctx_fail(c, NMD_E_INVALID, "LDS pattern %d out of range", pattern);
+  hipStream_t st = ctx_stream(c);
+  Buf sink;
+  if ((s = alloc(c, sink, 256))) return s;
+  Timer t;
+  if ((s = ctx_hip(c, hipEventCreate(&t.a), "hipEventCreate"))) return s;
+  if ((s = ctx_hip(c, hipEventCreate(&t.b), "hipEventCreate"))) return s;
+  if ((s = ctx_hip(c, hipEventRecord(t.a, st), "hipEventRecord"))) return s;
+  if (write)
+    hipLaunchKernelGGL(lds_write_kernel, dim3(blocks), dim3(256), 0, st, pattern, iters,
+                       (uint32_t *)sink.p);
+  else
+    hipLaunchKernelGGL(lds_read_kernel, dim3(blocks), dim3(256), 0, st, pattern, iters,
+                       (uint32_t *)sink.p);
+  if ((s = ctx_hip(c, hipGetLastError(), "lds probe"))) return s;
   if ((s = ctx_hip(c, hipEventRecord(t.b, st), "hipEventRecord"))) return s;
   if ((s = ctx_hip(c, hipEventSynchronize(t.b), "hipEventSynchronize"))) return s;
   float el = 0.0f;
