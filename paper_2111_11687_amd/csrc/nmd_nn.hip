@@ -76,8 +76,9 @@ constexpr int TX = 16, TY = 8;
 constexpr int HX = TX + 2, HY = TY + 2;
 template <int TZ>
 constexpr int halo_vox() { return HX * HY * (TZ + 2); }  // 720 or 1080 voxels
+__host__ __device__ constexpr int conv_tz_of(int cc, int ncb) { return ncb == 1 && cc == 16 ? 4 : 2; }
 template <int CC, int NCB>
-constexpr int conv_tz() { return NCB == 1 && CC == 16 ? 4 : 2; }
+constexpr int conv_tz() { return conv_tz_of(CC, NCB); }
 
 // LDS voxel pitch (elements).  On gfx950 the LDS has 64 four-byte banks,
 // and a ds_read_b128 serves 16 lanes per cycle: lanes 0-7 with 24-31, 8-15
@@ -997,7 +998,7 @@ nmd_status run_conv(nmd_ctx *c, int n, int d, int h, int w, const Src &src, int 
   a.tiles_y = (h + TY - 1) / TY;
   const int cc = chunk_of(cin);
   const int ncb = cout / 16;
-  const int tz = cc == 16 && ncb == 1 ? conv_tz<16, 1>() : 2;  // matches conv_tz
+  const int tz = conv_tz_of(cc, ncb);  // the launched kernel's tile depth
   a.tiles_z = (d + tz - 1) / tz;
   a.n_tiles = a.tiles_x * a.tiles_y * a.tiles_z;
   hipStream_t s = ctx_stream(c);
