@@ -170,9 +170,9 @@ def main():
     ap.add_argument("--positrons", action="store_true",
                     help="plain MC workloads: 18F positron range and the pair's "
                          "non-collinearity (FWHM 0.5 degrees)")
-    ap.add_argument("--emitter", choices=("pair", "lu177"), default="pair",
-                    help="plain MC workloads: the annihilation photon pair, or the 177Lu "
-                         "gamma lines and mean beta energy (tests/golden/lu177_decay.json)")
+    ap.add_argument("--emitter", choices=("pair", "lu177", "i131"), default="pair",
+                    help="plain MC workloads: the annihilation photon pair, or the 177Lu or "
+                         "131I gamma lines and mean beta energy (tests/golden/*_decay.json)")
     ap.add_argument("--tracking", choices=("global", "regions"), default="global",
                     help="plain MC and batch64 workloads: Woodcock majorant for the whole "
                          "phantom (global) or by region (the box of the dense voxels, and "
@@ -261,11 +261,11 @@ def bench_mc(args):
     iev = [P.MEAN_EXCITATION_EV[next(k for k in P.MATERIALS
                                      if tuple(P.MATERIALS[k][:2]) == tuple(m))]
            for m in prob.materials]
-    if args.emitter == "lu177":
-        lu = json.load(open(os.path.join(ROOT, "tests", "golden", "lu177_decay.json")))
-        B.nmd_set_emitter(eng.ctx, 0, [e * 1e-3 for e in lu["gamma_lines_kev"]],
-                          lu["gamma_yields_per_decay"], lu["beta_minus_mean_kev"] * 1e-3)
-        what += "; 177Lu gamma lines and mean beta energy in place of the photon pair"
+    if args.emitter != "pair":
+        dd = json.load(open(os.path.join(ROOT, "tests", "golden", args.emitter + "_decay.json")))
+        B.nmd_set_emitter(eng.ctx, 0, [e * 1e-3 for e in dd["gamma_lines_kev"]],
+                          dd["gamma_yields_per_decay"], dd["beta_minus_mean_kev"] * 1e-3)
+        what += "; %s gamma lines and mean beta energy in place of the photon pair" % dd["nuclide"]
     if args.positrons:
         B.nmd_set_positron(eng.ctx, 0, True, 0.5, iev)
         what += "; 18F positrons walked (CSDA), pair non-collinearity 0.5 deg FWHM"

@@ -161,9 +161,11 @@ nmd_status nmd_set_activity(nmd_ctx *ctx, int32_t phantom_id, const float *activ
  * the default) or [0.001, 0.3] MeV; mean_excitation_ev: host
  * double[n_materials], the mean excitation energy I of each material of
  * nmd_set_phantom, in (1, 10^4) eV.  The library tabulates each material's
- * range and inverse range on 256 nodes.  Resets the phantom's tallies;
- * re-registering the phantom drops the model; checkpoints do not record
- * it.  Synchronises the stream. */
+ * range and inverse range on 256 nodes, up to 345 keV (above the Compton
+ * electrons of 511 keV photons): with an emitter line above 0.511 MeV on
+ * the phantom the call returns NMD_E_UNSUPPORTED.  Resets the phantom's
+ * tallies; re-registering the phantom drops the model; checkpoints do not
+ * record it.  Synchronises the stream. */
 nmd_status nmd_set_electrons(nmd_ctx *ctx, int32_t phantom_id, double cutoff_mev,
                              const double *mean_excitation_ev);
 
@@ -199,10 +201,10 @@ nmd_status nmd_set_positron(nmd_ctx *ctx, int32_t phantom_id, int32_t on, double
                             const double *mean_excitation_ev);
 
 /* Gamma + beta emitters in place of the annihilation pair (the other
- * radionuclides Section 4 names, such as 177Lu).  With n_lines > 0 or
+ * radionuclides Section 4 names, 177Lu and 131I).  With n_lines > 0 or
  * beta_mean_mev > 0, every decay of the activity source emits at most one
- * photon: line i, of energy energy_mev[i] in (0.001, 0.511] MeV (the
- * cross-section grid ends at 511 keV), with probability yield[i] per decay
+ * photon: line i, of energy energy_mev[i] in (0.001, 1] MeV, with
+ * probability yield[i] per decay
  * (yields >= 0, summing to at most 1), in an isotropic direction; and it
  * leaves beta_mean_mev, the mean beta kinetic energy, in the decay voxel
  * (booked as NMD_LEDGER_DEP_BETA).  Per decay the draws are: the decay
@@ -212,8 +214,12 @@ nmd_status nmd_set_positron(nmd_ctx *ctx, int32_t phantom_id, int32_t on, double
  * together with nmd_set_positron (NMD_E_STATE).  Pencil-beam runs are
  * unchanged.  Resets the phantom's tallies; re-registering the phantom drops
  * it; checkpoints do not record it; graphs captured before the call refuse
- * to launch.  energy_mev, yield: host double[n_lines].  Errors:
- * NMD_E_STATE, NMD_E_INVALID.  Synchronises the stream. */
+ * to launch.  A line above 0.511 MeV puts the phantom's cross sections on
+ * a wider grid (256 nodes from 1 keV to 1 MeV, in place of 1 to 511 keV)
+ * and excludes Compton electron transport (NMD_E_UNSUPPORTED: its range
+ * tables end at 345 keV).  energy_mev, yield: host double[n_lines].
+ * Errors: NMD_E_STATE, NMD_E_INVALID, NMD_E_UNSUPPORTED.  Synchronises the
+ * stream. */
 nmd_status nmd_set_emitter(nmd_ctx *ctx, int32_t phantom_id, int32_t n_lines,
                            const double *energy_mev, const double *yield, double beta_mean_mev);
 

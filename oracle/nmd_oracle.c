@@ -66,6 +66,9 @@
 #define ORC_NGRID 256                     /* energy nodes               */
 #define ORC_EGRID_MIN 1.0e-3              /* 1 keV                      */
 #define ORC_EGRID_RATIO 511.0             /* top node = 511 keV         */
+#define ORC_EGRID_RATIO_W 1000.0          /* the wide grid: top 1 MeV, for
+                                             emitter lines above 511 keV */
+#define ORC_LINE_MAX_MEV 1.0              /* emitter lines up to its top */
 #define ORC_EREF 0.030                    /* anchor energy              */
 #define ORC_ZREF 7.4                      /* anchor Z                   */
 #define ORC_KAPPA (1.0 + 1.0 / 16384.0)   /* majorant inflation         */
@@ -114,11 +117,14 @@ double orc_sigma_kn(double e_mev)
   return 2.0 * ORC_PI * ORC_RE_CM * ORC_RE_CM * (t1 + t2 - t3);
 }
 
-/* Energy of grid node i: 1 keV * 511^(i/255), in MeV. */
-double orc_grid_energy(int i)
+/* Energy of node i of the grid from 1 keV to 1 keV * ratio: 1 keV *
+ * ratio^(i/255), in MeV.  The pair's grid has ratio 511; a run whose emitter
+ * has a line above 511 keV uses the wide grid, ratio 1000. */
+static double grid_energy_r(int i, double ratio)
 {
-  return ORC_EGRID_MIN * pow(ORC_EGRID_RATIO, (double)i / (double)(ORC_NGRID - 1));
+  return ORC_EGRID_MIN * pow(ratio, (double)i / (double)(ORC_NGRID - 1));
 }
+double orc_grid_energy(int i) { return grid_energy_r(i, ORC_EGRID_RATIO); }
 
 /* Mass attenuation of one process at node energy e (cm^2/g).
  * process: 1 Compton, 2 photoelectric, 3 Rayleigh. */
@@ -142,9 +148,9 @@ double orc_mass_atten_closed(int process, double z, double z_over_a, double e)
 }
 
 /* Log-log interpolation on the grid of a table of ln-values. */
-static void grid_locate(double e, int *i_out, double *f_out)
+static void grid_locate(double ratio, double e, int *i_out, double *f_out)
 {
-  const double dl = log(ORC_EGRID_RATIO) / (double)(ORC_NGRID - 1);
+  const double dl = log(ratio) / (double)(ORC_NGRID - 1);
   double t = (log(e) - log(ORC_EGRID_MIN)) / dl;
   int i = (int)floor(t);
   if (i < 0) i = 0;
@@ -429,7 +435,8 @@ typedef struct {
   /* A gamma + beta emitter in place of the annihilation pair (n_lines > 0 or
    * beta_mean_mev > 0; activity source only): a decay emits at most one
    * photon, line i with probability line_yield[i] (the yields sum to at most
-   * 1), isotropic, of energy line_mev[i] (<= 0.511 MeV), and leaves
+   * 1), isotropic, of energy line_mev[i] (<= 1 MeV; a line above 0.511 MeV
+   * puts the run on the wide grid and excludes the electron option), and leaves
    * beta_mean_mev in its voxel. */
   int32_t n_lines;
   const double *line_mev;
@@ -457,17 +464,19 @@ typedef struct {
   double out_ratio;
   double box_lo[3], box_hi[3];
   int has_out;
+  double grid_ratio; /* ORC_EGRID_RATIO, or ORC_EGRID_RATIO_W */
 } orc_tables;
 
 #define ORC_INNER_RHO 0.01f /* g/cm^3, compared in single precision as stored */
 
-static void build_tables(const orc_phantom *ph, orc_tables *t)
+static void build_tables(const orc_phantom *ph, orc_tables *t, double ratio)
 {
+  t->grid_ratio = ratio;
   for (int m = 0; m < ph->n_mat; ++m)
     for (int p = 0; p < 3; ++p)
       for (int i = 0; i < ORC_NGRID; ++i)
-        t->ln_mu_rho[m][p][i] =
-            log(orc_mass_atten_closed(p + 1, ph->z_eff[m], ph->z_over_a[m], orc_grid_energy(i)));
+        t->ln_mu_rho[m][p][i] = log(orc_mass_atten_closed(p + 1, ph->z_eff[m], ph->z_over_a[m],
+                                                          grid_energy_r(i, ratio)));
   /* majorant: mu is linear in density, so the maximum over all voxels of
    * a material is reached at that material's largest density. */
   double rho_max[8];
@@ -542,7 +551,7 @@ static void eval_mu_rho(const orc_tables *t, int n_mat, double e, double out[8][
 {
   int i;
   double f;
-  grid_locate(e, &i, &f);
+  grid_locate(t->grid_ratio, e, &i, &f);
   for (int m = 0; m < n_mat; ++m)
     for (int p = 0; p < 3; ++p) out[m][p] = loglog(t->ln_mu_rho[m][p], i, f);
 }
@@ -551,7 +560,7 @@ static double eval_major(const orc_tables *t, double e)
 {
   int i;
   double f;
-  grid_locate(e, &i, &f);
+  grid_locate(t->grid_ratio, e, &i, &f);
   return ORC_KAPPA * loglog(t->ln_major, i, f);
 }
 
@@ -1323,9 +1332,11 @@ int orc_run(const orc_phantom *ph, const orc_opts *op, orc_tally *tal)
       return -1;
     double ysum = 0.0;
     for (int i = 0; i < op->n_lines; ++i) {
-      if (!(op->line_mev[i] > 0.001 && op->line_mev[i] <= ORC_E0_MEV) ||
+      if (!(op->line_mev[i] > 0.001 && op->line_mev[i] <= ORC_LINE_MAX_MEV) ||
           !(op->line_yield[i] >= 0.0))
         return -1;
+      /* the electron range tables end above the Compton electrons of 511 keV */
+      if (op->line_mev[i] > ORC_E0_MEV && op->electron_cutoff_mev > 0.0) return -1;
       ysum += op->line_yield[i];
     }
     if (ysum > 1.0 + 1e-12) return -1;
@@ -1337,8 +1348,11 @@ int orc_run(const orc_phantom *ph, const orc_opts *op, orc_tally *tal)
     if (ph->label && ph->label[v] > ph->n_organs) return -2;
   }
 
+  /* an emitter line above 511 keV takes the wide grid */
+  int wide = 0;
+  for (int i = 0; i < op->n_lines; ++i) wide = wide || op->line_mev[i] > ORC_E0_MEV;
   orc_tables *tab = (orc_tables *)malloc(sizeof(orc_tables));
-  build_tables(ph, tab);
+  build_tables(ph, tab, wide ? ORC_EGRID_RATIO_W : ORC_EGRID_RATIO);
 
   orc_ctx cx;
   cx.ph = ph;
@@ -1592,7 +1606,7 @@ double orc_mass_atten_interp(int process, double z, double z_over_a, double e)
     lt[i] = log(orc_mass_atten_closed(process, z, z_over_a, orc_grid_energy(i)));
   int i;
   double f;
-  grid_locate(e, &i, &f);
+  grid_locate(ORC_EGRID_RATIO, e, &i, &f);
   return loglog(lt, i, f);
 }
 
@@ -1600,7 +1614,7 @@ double orc_mass_atten_interp(int process, double z, double z_over_a, double e)
 double orc_majorant(const orc_phantom *ph, double e)
 {
   orc_tables *tab = (orc_tables *)malloc(sizeof(orc_tables));
-  build_tables(ph, tab);
+  build_tables(ph, tab, ORC_EGRID_RATIO);
   const double m = eval_major(tab, e);
   free(tab);
   return m;

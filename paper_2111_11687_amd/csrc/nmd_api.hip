@@ -62,6 +62,7 @@ struct Phantom {
   double dx = 0, dy = 0, dz = 0;  // cm
   uint64_t nvox = 0;
   DevBuf rec, alias, tally, organ, ledger, stats, major, organ_w;  // rec: u16 per voxel
+  DevBuf major_w;  // the wide grid's majorant nodes, then its Klein-Nishina nodes
   DevBuf n_done_dev, organ_acc;      // device history counter; organ reduction output
   uint64_t gen = 0;                  // changes whenever the device buffers change
   std::vector<int64_t> organ_count;  // voxels per label 0..n_org
@@ -85,6 +86,8 @@ struct Phantom {
   float em_e[kMaxLines] = {}, em_beta = 0.0f;
   int32_t box0[3] = {0, 0, 0}, box1[3] = {0, 0, 0};  // inner box, voxel indices [box0, box1)
   double out_ratio = 0.0;  // outer majorant / inner majorant (0: no outer region)
+  double out_ratio_w = 0.0;  // the same on the wide grid
+  bool wide = false;  // an emitter line above 511 keV: the wide grid's tables
   int32_t tracking = NMD_TRACK_GLOBAL;  // NMD_TRACK_* (nmd_set_tracking)
   float e_cut = 0.0f, e_inv_dt = 0.0f;
   uint64_t geom_hash = 0;   // FNV-1a of the voxel records, for checkpoints
@@ -167,6 +170,7 @@ double sigma_kn(double e) {
           (1.0 + 3.0 * k) / (a * a));
 }
 double grid_e(int i) { return kEGridMin * std::pow(kEGridRatio, (double)i / (kNGrid - 1)); }
+double grid_e_w(int i) { return kEGridMin * std::pow(kEGridRatioW, (double)i / (kNGrid - 1)); }
 
 // Coefficients of one (material, density) pair, FP64: mu_C = cC * N_A
 // sigma_KN(E), mu_PE = cPE / E^3, mu_R = cR / E^2 (cm^-1).
@@ -304,7 +308,8 @@ PhantomDesc make_desc(int32_t id, const Phantom &p) {
   d.organ = p.organ.as<double2>();
   d.ledger = p.ledger.as<double>();
   d.stats = p.stats.as<unsigned long long>();
-  d.ln2_major = p.major.as<float>();
+  d.ln2_major = p.wide ? p.major_w.as<float>() : p.major.as<float>();
+  d.wide = p.wide ? 1 : 0;
   d.organ_w = p.organ_w.as<double>();
   d.n_done = p.n_done_dev.as<unsigned long long>();
   d.nx = p.nx;
@@ -335,8 +340,9 @@ PhantomDesc make_desc(int32_t id, const Phantom &p) {
     d.bcm0[a] = (float)(lo * h[a]);
     d.bcm1[a] = (float)(hi * h[a]);
   }
-  d.out_ratio = regions ? (float)p.out_ratio : 0.0f;
-  d.inv_out_ratio = regions ? (float)(1.0 / p.out_ratio) : 0.0f;
+  const double orat = p.wide ? p.out_ratio_w : p.out_ratio;
+  d.out_ratio = regions ? (float)orat : 0.0f;
+  d.inv_out_ratio = regions ? (float)(1.0 / orat) : 0.0f;
   d.e_tab = p.e_tab.as<float>();
   d.e_inv_dr = p.e_inv_dr.as<float>();
   d.e_slot = p.e_slot.as<uint8_t>();
@@ -921,10 +927,13 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
     p.geom_hash = h;
   }
 
-  // majorant nodes: max over this phantom's pairs of the total attenuation
-  std::vector<float> maj(kNGrid);
-  for (int i = 0; i < kNGrid; ++i) {
-    const double e = grid_e(i);
+  // majorant nodes: max over this phantom's pairs of the total attenuation,
+  // on the pair's grid (maj) and on the wide grid (maj_w, followed by the
+  // wide grid's Klein-Nishina nodes)
+  std::vector<float> maj(kNGrid), maj_w(2 * kNGrid);
+  for (int i = 0; i < 2 * kNGrid; ++i) {
+    const bool w = i >= kNGrid;
+    const double e = w ? grid_e_w(i - kNGrid) : grid_e(i);
     const double s_na = kNA * sigma_kn(e);
     double mx = 0.0;
     for (size_t q = 0; q < pal.size(); ++q) {
@@ -934,7 +943,8 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
       const double mu = cc * s_na + cpe / (e * e * e) + cr / (e * e);
       mx = std::max(mx, mu);
     }
-    maj[i] = round_up_f32(std::log2(mx));
+    (w ? maj_w[i - kNGrid] : maj[i]) = round_up_f32(std::log2(mx));
+    if (w) maj_w[i] = (float)std::log2(s_na);
   }
   // the inner box: the bounding box of the voxels at least kInnerRho dense;
   // the (material, density) pairs outside it set the outer majorant
@@ -969,9 +979,10 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
   // over the energy nodes, of the outer voxels' attenuation to the inner
   // majorant node (log-log interpolation keeps the bound between nodes),
   // widened by 2^-16 for the FP32 product
-  double ratio = 0.0;
-  for (int i = 0; any_out && i < kNGrid; ++i) {
-    const double e = grid_e(i);
+  double ratio = 0.0, ratio_w = 0.0;
+  for (int i = 0; any_out && i < 2 * kNGrid; ++i) {
+    const bool w = i >= kNGrid;
+    const double e = w ? grid_e_w(i - kNGrid) : grid_e(i);
     const double s_na = kNA * sigma_kn(e);
     double mx = 0.0;
     for (size_t q = 0; q < pal.size(); ++q) {
@@ -980,9 +991,13 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
       pal_coeffs(pal[q].z, pal[q].zoa, (double)pal[q].rho, cc, cpe, cr);
       mx = std::max(mx, cc * s_na + cpe / (e * e * e) + cr / (e * e));
     }
-    ratio = std::max(ratio, mx / std::exp2((double)maj[i]));
+    if (w)
+      ratio_w = std::max(ratio_w, mx / std::exp2((double)maj_w[i - kNGrid]));
+    else
+      ratio = std::max(ratio, mx / std::exp2((double)maj[i]));
   }
   p.out_ratio = any_out ? ratio * (1.0 + 1.0 / 65536.0) : 0.0;
+  p.out_ratio_w = any_out ? ratio_w * (1.0 + 1.0 / 65536.0) : 0.0;
   for (int a = 0; a < 3; ++a) {
     p.box0[a] = b0[a];
     p.box1[a] = b1[a];
@@ -997,6 +1012,7 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
       (s = dev_alloc(c, p.ledger, 8 * sizeof(double))) ||
       (s = dev_alloc(c, p.stats, 16 * sizeof(unsigned long long))) ||
       (s = dev_alloc(c, p.major, kNGrid * sizeof(float))) ||
+      (s = dev_alloc(c, p.major_w, 2 * kNGrid * sizeof(float))) ||
       (s = dev_alloc(c, p.organ_w, (n_organs + 1) * sizeof(double))) ||
       (s = dev_alloc(c, p.n_done_dev, 2 * sizeof(unsigned long long))) ||
       (s = dev_alloc(c, p.organ_acc, (n_organs + 1) * 2 * sizeof(double))))
@@ -1006,6 +1022,8 @@ nmd_status nmd_set_phantom(nmd_ctx *c, int32_t id, int32_t nx, int32_t ny, int32
                             c->stream));
   HIP_TRY(c, hipMemcpyAsync(p.major.p, maj.data(), kNGrid * sizeof(float), hipMemcpyHostToDevice,
                             c->stream));
+  HIP_TRY(c, hipMemcpyAsync(p.major_w.p, maj_w.data(), 2 * kNGrid * sizeof(float),
+                            hipMemcpyHostToDevice, c->stream));
 
   HIP_TRY(c, hipMemcpyAsync(p.organ_w.p, ow.data(), ow.size() * sizeof(double),
                             hipMemcpyHostToDevice, c->stream));
@@ -1101,6 +1119,9 @@ nmd_status nmd_set_electrons(nmd_ctx *c, int32_t id, double cutoff_mev,
   } else {
     if (!(cutoff_mev >= 0.001 && cutoff_mev <= 0.3))
       return fail(c, NMD_E_INVALID, "electron cutoff must be 0 or lie in [0.001, 0.3] MeV");
+    if (p->wide)
+      return fail(c, NMD_E_UNSUPPORTED, "the emitter has a line above 0.511 MeV: the electron "
+                  "range tables end below its Compton electrons");
     if (!mean_excitation_ev)
       return fail(c, NMD_E_INVALID, "mean excitation energies are required");
     for (int m = 0; m < p->n_mat; ++m)
@@ -1212,8 +1233,11 @@ nmd_status nmd_set_emitter(nmd_ctx *c, int32_t id, int32_t n_lines, const double
     return fail(c, NMD_E_INVALID, "line energies and yields are required");
   double cum = 0.0;
   for (int i = 0; i < n_lines; ++i) {
-    if (!(energy_mev[i] > 0.001 && energy_mev[i] <= 0.511))
-      return fail(c, NMD_E_INVALID, "line %d: energy must lie in (0.001, 0.511] MeV", i);
+    if (!(energy_mev[i] > 0.001 && energy_mev[i] <= kLineMax))
+      return fail(c, NMD_E_INVALID, "line %d: energy must lie in (0.001, %g] MeV", i, kLineMax);
+    // the electron range tables end above the Compton electrons of 511 keV
+    if (energy_mev[i] > 0.511 && p->e_cut > 0.0f)
+      return fail(c, NMD_E_UNSUPPORTED, "line %d above 0.511 MeV with Compton electrons on", i);
     if (!(yield[i] >= 0.0)) return fail(c, NMD_E_INVALID, "line %d: negative yield", i);
     cum += yield[i];
   }
@@ -1230,6 +1254,8 @@ nmd_status nmd_set_emitter(nmd_ctx *c, int32_t id, int32_t n_lines, const double
     p->em_e[i] = i < p->em_n ? (float)energy_mev[i] : 0.0f;
   }
   p->em_beta = on ? (float)beta_mean_mev : 0.0f;
+  p->wide = false;
+  for (int i = 0; i < p->em_n; ++i) p->wide = p->wide || energy_mev[i] > 0.511;
   p->gen = c->next_gen++;
   if (p->has_activity && (s = zero_tallies(c, *p))) return s;
   return upload_desc(c, id, *p);

@@ -49,6 +49,13 @@ constexpr double kERef = 0.030;                 // MeV, cross-section anchor
 constexpr double kZRef = 7.4;
 constexpr double kEGridMin = 1.0e-3;            // MeV
 constexpr double kEGridRatio = 511.0;
+// The wide grid of a phantom whose emitter has a line above 511 keV: the same
+// 256 nodes from 1 keV to 1 MeV, in that phantom's own tables (the pair and
+// lower lines keep the grid above).  Same first node, so only the spacing
+// differs: (kNGrid - 1) / log2(1000).
+constexpr double kEGridRatioW = 1000.0;
+constexpr float kInvDl2W = (float)(255.0 / 9.965784284662087);
+constexpr double kLineMax = 1.0;  // MeV, the emitter lines the wide grid holds
 constexpr float kE0 = 0.511f;                   // annihilation photon energy
 constexpr float kKappa = 1.0f + 1.0f / 16384.0f;  // majorant inflation
 
@@ -106,6 +113,9 @@ struct PhantomDesc {
   double em_cum[kMaxLines];
   float em_e[kMaxLines];
   float em_beta;
+  // 1: ln2_major holds the wide grid's majorant nodes followed by its
+  // Klein-Nishina nodes, and energies use the wide grid's spacing
+  int32_t wide;
 };
 
 // Per-run fields of one phantom of a launch.

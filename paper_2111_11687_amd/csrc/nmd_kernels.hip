@@ -230,6 +230,16 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
     }
   };
 
+  // Energy factors at e on the wave's phantom's grid: the pair's (its
+  // Klein-Nishina nodes in LDS) or, for an emitter with a line above 511 keV
+  // (electron instantiation only), the wide grid, whose Klein-Nishina nodes
+  // follow its majorant nodes in global memory.  D is wave-uniform.
+  auto ep_at = [&](float e) -> EnergyParams {
+    if (kElectrons && D->wide)
+      return energy_params(e, D->ln2_major + kNGrid, wl.maj, P.l2emin, kInvDl2W);
+    return energy_params(e, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+  };
+
   // load the wave's per-phantom LDS tables
   auto enter_phantom = [&]() {
     for (int i = lane; i < kNGrid; i += 64) wl.maj[i] = G(D->ln2_major)[i];
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
     }
     wave_lds_sync();
     // every photon starts at the emission energy: its factors, once
-    const EnergyParams e0 = energy_params(kE0, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+    const EnergyParams e0 = ep_at(kE0);
     if (lane == 0) {
       wa.ep0[0] = e0.sig;
       wa.ep0[1] = e0.gpe;
@@ -788,7 +798,7 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
         start_photon();
         E = D->em_e[line];
         atomicAdd(&wa.ledger[0], (double)E);
-        ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+        ep = ep_at(E);
         if (kRegions && (psteps & kOuter)) {
           ep.mu_hat *= D->out_ratio;
           ep.inv_mu_ln2 *= D->inv_out_ratio;
@@ -961,7 +971,7 @@ __global__ __launch_bounds__(kBlock, kElectrons ? 2 : NMD_TRANSPORT_MIN_BLOCKS) 
               dep = walked ? (double)E : dep + (double)E;
               pdone = true;
             } else {
-              ep = energy_params(E, s_kn, wl.maj, P.l2emin, P.inv_dl2);
+              ep = ep_at(E);
               if (kRegions && (psteps & kOuter)) {  // a Compton event outside the inner box
                 ep.mu_hat *= D->out_ratio;
                 ep.inv_mu_ln2 *= D->inv_out_ratio;

@@ -1,5 +1,5 @@
 """Gamma + beta emitters on the device (nmd_set_emitter), with the 177Lu
-data of tests/golden/lu177_decay.json: history by history against the
+and 131I data of tests/golden/*_decay.json: history by history against the
 oracle's emitter on the same streams, statistically against exact traversal
 on the patient, and the switch's semantics."""
 import json
@@ -13,19 +13,28 @@ from paper_2111_11687_amd import binding as B
 from paper_2111_11687_amd import phantoms as P
 
 pytestmark = pytest.mark.gpu
-LU = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "lu177_decay.json")))
-LINES = [e * 1e-3 for e in LU["gamma_lines_kev"]]
-YIELDS = LU["gamma_yields_per_decay"]
-BETA = LU["beta_minus_mean_kev"] * 1e-3
+
+
+def _nuclide(name):
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", name + "_decay.json")))
+    return ([e * 1e-3 for e in d["gamma_lines_kev"]], d["gamma_yields_per_decay"],
+            d["beta_minus_mean_kev"] * 1e-3)
+
+
+# 131I's lines reach 723 keV: its phantom takes the wide grid (1 keV to 1 MeV)
+EMITTERS = {"lu177": _nuclide("lu177"), "i131": _nuclide("i131")}
+LINES, YIELDS, BETA = EMITTERS["lu177"]
 
 
 def _balance(led):
     return ledger_balance(led) + led["dep_beta"] / led["emitted"]
 
 
-def test_emitter_replays_history_by_history(engine, orc):
+@pytest.mark.parametrize("nuclide", ["lu177", "i131"])
+def test_emitter_replays_history_by_history(engine, orc, nuclide):
     """The slab's point source: the line choice, the beta deposit and the
     photon's events replay the oracle's emitter draw for draw."""
+    LINES, YIELDS, BETA = EMITTERS[nuclide]
     prob = P.slab_phantom(n=64, voxel_mm=6.0)
     engine.set_problem(61, prob)
     B.nmd_set_emitter(engine.ctx, 61, LINES, YIELDS, BETA)
@@ -49,10 +58,11 @@ def test_emitter_replays_history_by_history(engine, orc):
     assert abs(st["photons"] / n - sum(YIELDS)) < 5 * np.sqrt(sum(YIELDS) / n)
 
 
-def test_emitter_statistical_parity_patient(engine, orc):
-    """The full-size patient with the 177Lu emitter against the
-    exact-traversal oracle with the same emitter: every organ within three
-    combined sigma."""
+@pytest.mark.parametrize("nuclide", ["lu177", "i131"])
+def test_emitter_statistical_parity_patient(engine, orc, nuclide):
+    """The full-size patient with the emitter against the exact-traversal
+    oracle with the same emitter: every organ within three combined sigma."""
+    LINES, YIELDS, BETA = EMITTERS[nuclide]
     prob = P.patient_phantom()
     engine.set_problem(62, prob)
     B.nmd_set_emitter(engine.ctx, 62, LINES, YIELDS, BETA)
@@ -72,13 +82,23 @@ def test_emitter_statistical_parity_patient(engine, orc):
 def test_emitter_switch_and_validation(engine):
     prob = P.patient_phantom(shape=(50, 40, 40), voxel_mm=(12.0, 12.0, 18.0), seed=45)
     engine.set_problem(62, prob)
-    for bad in (([0.6], [0.1], 0.1), ([0.1], [0.7, 0.5][:1] + [0.0], 0.1),
+    for bad in (([1.2], [0.1], 0.1), ([0.1], [0.7, 0.5][:1] + [0.0], 0.1),
                 ([0.1, 0.2], [0.6, 0.5], 0.1), ([0.1], [0.1], -0.1)):
         with pytest.raises((B.NmdError, ValueError)):
             B.nmd_set_emitter(engine.ctx, 62, *bad)
+    iev = [75.0] * len(prob.materials)
+    # lines above 511 keV and Compton electron transport exclude each other
+    B.nmd_set_emitter(engine.ctx, 62, *EMITTERS["i131"])
+    with pytest.raises(B.NmdError, match="NMD_E_UNSUPPORTED"):
+        B.nmd_set_electrons(engine.ctx, 62, 0.2, iev)
+    B.nmd_set_emitter(engine.ctx, 62)
+    B.nmd_set_electrons(engine.ctx, 62, 0.2, iev)
+    with pytest.raises(B.NmdError, match="NMD_E_UNSUPPORTED"):
+        B.nmd_set_emitter(engine.ctx, 62, *EMITTERS["i131"])
+    B.nmd_set_electrons(engine.ctx, 62, 0.0, None)
     B.nmd_set_emitter(engine.ctx, 62, LINES, YIELDS, BETA)
     with pytest.raises(B.NmdError, match="NMD_E_STATE"):
-        B.nmd_set_positron(engine.ctx, 62, True, 0.5, [75.0] * len(prob.materials))
+        B.nmd_set_positron(engine.ctx, 62, True, 0.5, iev)
     engine.run(62, 100_000, 3)
     led = engine.ledger(62)
     assert led["dep_beta"] == pytest.approx(100_000 * BETA, rel=1e-6)
