@@ -108,3 +108,40 @@ def test_emitter_switch_and_validation(engine):
     led = engine.ledger(62)
     assert led["dep_beta"] == 0.0
     assert led["emitted"] == pytest.approx(100_000 * 2 * 0.511, rel=1e-6)
+
+
+def test_wide_and_pair_grid_phantoms_in_one_launch():
+    """A 177Lu phantom (the pair's grid) and a 131I phantom (the wide grid)
+    in one batched launch: each wave takes its phantom's grid, so each
+    phantom gets exactly what its own launch gives."""
+    def small(seed):
+        return P.patient_phantom(shape=(50, 40, 40), voxel_mm=(12.0, 12.0, 18.0), seed=seed)
+
+    def snap(eng, pid):
+        s, s2, n = eng.tallies(pid)
+        st = eng.stats(pid)
+        for k in ("claims", "max_merged"):  # schedule-dependent
+            st.pop(k)
+        return s.cpu().numpy(), s2.cpu().numpy(), n, st, eng.ledger(pid)
+
+    a, b = small(51), small(52)
+    n, seed = 300_000, 93
+    sep, bat = B.Engine(0), B.Engine(0)
+    try:
+        for e in (sep, bat):
+            e.set_problem(1, a)
+            e.set_problem(2, b)
+            B.nmd_set_emitter(e.ctx, 1, *EMITTERS["lu177"])
+            B.nmd_set_emitter(e.ctx, 2, *EMITTERS["i131"])
+        sep.run(1, n, seed)
+        sep.run(2, n, seed)
+        B.nmd_run_histories(bat.ctx, -1, n, seed, None)
+        for pid in (1, 2):
+            x, y = snap(sep, pid), snap(bat, pid)
+            assert x[2] == y[2] and x[3] == y[3]
+            assert np.allclose(x[0], y[0], rtol=1e-12, atol=0)
+            assert np.allclose(x[1], y[1], rtol=1e-12, atol=0)
+            assert abs(_balance(y[4])) < 1e-9
+    finally:
+        sep.close()
+        bat.close()
